@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MM / HV lattice-Boltzmann Maxwell steppers on one MI355X.
+
+Workload: the 256^3 Hertz-dipole lattice (vacuum, 16-cell quadratic sigma
+sponge on every face, soft point current J_z = sin(2 pi n / 40) at the centre,
+three field probes recorded every step).  One benchmark step is one time step
+of the whole lattice: gather with in-place streaming, collision, sources,
+scatter and the fused FP64 probe recording.  The headline value is the MM
+model with FP32 population storage; the HV model and BF16 storage are timed
+the same way and reported under "variants".
+
+Prints one JSON line.  `value` is lattice updates per second (MLUPS) with the
+state already resident in HBM; `roofline` prices the step kernel against the
+MI355X HBM peak using the algorithmic bytes per lattice update (every
+population read once and written once, plus 12 B of media).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+BYTES_PER_LU = {("mm", "f32"): 2 * 50 * 4 + 12, ("mm", "bf16"): 2 * 50 * 2 + 12,
+                ("hv", "f32"): 2 * 36 * 4 + 12, ("hv", "bf16"): 2 * 36 * 2 + 12}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2309_08068_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(model: str, storage: str, n: int):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    v = rec.get("variants", {}).get(f"{model}_{storage}")
+    if not v or v.get("cells") != n:
+        return None
+    return v.get("bytes_per_launch")
+
+
+def time_variant(model: str, storage: str, n: int, steps: int, warmup: int):
+    import torch
+    from paper_2309_08068_amd import inputs, lbem
+
+    w = inputs.dipole(model, n=n, steps=steps)
+    lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=0.0)
+    lat.set_probes(w.probes, warmup + 2 * steps + 1)
+    stream = torch.cuda.current_stream()
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    # whole-job timing of `steps` steps
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-launch duration of the step kernel from HIP events on the library's stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    kernel_ms = e0.elapsed_time(e1) / steps
+    cells = w.n
+    mlups = cells * steps / wall / 1e6
+    bpl = BYTES_PER_LU[(model, storage)]
+    achieved = bpl * cells / (kernel_ms * 1e-3) / 1e9
+    del lat
+    torch.cuda.empty_cache()
+    return dict(model=model, storage=storage, cells=cells, mlups=mlups, ms_per_step=wall * 1e3 / steps,
+                kernel_ms=kernel_ms, bytes_per_lu=bpl, achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS,
+                traffic=measured_traffic(model, storage, cells))
+
+
+def cpu_baseline(n: int, sample_steps: int):
+    """The FP64 oracle on the host cores: a few steps of the same 256^3 MM dipole lattice."""
+    import oracle
+    from paper_2309_08068_amd import inputs
+
+    oracle.build(force=False)
+    w = inputs.dipole("mm", n=n, steps=sample_steps)
+    P = oracle.Problem("mm", w.shape, sigma=w.sigma, currents=w.currents)
+    f = oracle.init(P, *w.fields0())
+    t0 = time.perf_counter()
+    oracle.run(P, f, 0, sample_steps, probes=w.probes)
+    dt = time.perf_counter() - t0
+    return {"value": w.n * sample_steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{sample_steps} steps of the {n}^3 MM dipole lattice, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="lattice edge (the workload is n^3)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--only", default="", help="comma list of model_storage variants to time")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
+              "not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    variants = [("mm", "f32"), ("mm", "bf16"), ("hv", "f32"), ("hv", "bf16")]
+    if args.only:
+        keep = set(args.only.split(","))
+        variants = [v for v in variants if f"{v[0]}_{v[1]}" in keep]
+    results = {}
+    for model, storage in variants:
+        r = time_variant(model, storage, args.n, args.steps, args.warmup)
+        results[f"{model}_{storage}"] = r
+        print(f"# {model} {storage}: {r['mlups']:.0f} MLUPS, step kernel {r['kernel_ms']:.3f} ms, "
+              f"{r['achieved_gbs']:.0f} GB/s ({100 * r['frac']:.1f}% of peak)", file=sys.stderr, flush=True)
+    head = results.get("mm_f32") or next(iter(results.values()))
+    traffic = head["traffic"]
+    line = {
+        "metric": "MLUPS & %HBM peak, MM/HV 256^3 FP32 vs BF16 storage; adjoint/forward time",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"hertz_dipole_{args.n}^3", "model": head["model"], "storage": head["storage"],
+                   "cells": head["cells"], "sponge": 16, "source": "point J_z = sin(2 pi n / 40)",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(head["frac"], 4),
+                     "traffic": None if traffic is None else round(traffic / 1e9 / (head["kernel_ms"] * 1e-3), 1),
+                     "kernel": f"step_kernel<{head['model'].upper()}, {head['storage']}>",
+                     "bytes_per_lu": head["bytes_per_lu"], "kernel_ms": round(head["kernel_ms"], 4)},
+        "variants": {k: {"mlups": round(v["mlups"], 1), "achieved_gbs": round(v["achieved_gbs"], 1),
+                         "frac": round(v["frac"], 4), "kernel_ms": round(v["kernel_ms"], 4),
+                         "bytes_per_lu": v["bytes_per_lu"]} for k, v in results.items()},
+        "adjoint_over_forward": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * lbem.h -- C ABI of the MI355X (gfx950) lattice-Boltzmann Maxwell library.
+ *
+ * Two schemes from arXiv 2309.08068 are provided:
+ *   LBEM_MM  Mendoza-Munoz model (Section II): 50 populations per cell, 12 face
+ *            diagonal velocities in three planes plus two rest populations,
+ *            lattice constants eps0 = 1, mu0 = 2 (vacuum speed 1/sqrt(2)).
+ *   LBEM_HV  modified Hauser-Verhey model (Section III): 6 axis velocities, one
+ *            electric and one magnetic 3-vector population each (36 scalars),
+ *            with the current source term T_i = -(J.v_i) v_i / 2 of eq.
+ *            (SourceTermHV); lattice constants eps0 = mu0 = 3 (speed 1/3).
+ * One time step (Appendix B) = collision with tau = 1/2 (moments, constitutive
+ * relations and current, equilibria, f' = 2 f_eq - f [+ T]), imposition of hard
+ * sources, advection f(x + v_q) <- f'(x).  All boundaries are periodic.
+ *
+ * Conventions shared by every call:
+ *   - Cells are ordered x fastest: cell = x + nx * (y + ny * z); N = nx ny nz,
+ *     1 <= N < 2^31.  Vector fields are [3][N] (component-major) float arrays.
+ *   - "dev" pointers are device (HBM) pointers of the GPU that is current when
+ *     the lattice is created; "host" pointers are ordinary host memory.
+ *   - The caller owns every buffer, including the workspace; the library never
+ *     allocates device memory.  A workspace must stay valid until destroy.
+ *   - All work is enqueued on the stream given at create (or set_stream) and is
+ *     asynchronous unless stated; outputs are valid after that stream syncs.
+ *   - Functions return LBEM_OK or a negative lbem_status; lbem_last_error()
+ *     gives a message for the calling thread.  Arguments are validated on the
+ *     host before anything is enqueued; a failed call changes nothing.
+ *   - A lattice handle must not be used from two threads at once.
+ */
+#ifndef LBEM_H
+#define LBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBEM_OK = 0,
+    LBEM_EINVAL = -1,      /* bad argument (null, size, range, mismatched state) */
+    LBEM_ENOMEM = -2,      /* workspace or buffer smaller than required */
+    LBEM_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+    LBEM_EUNSTABLE = -4,   /* media outside the stable range of the scheme */
+    LBEM_ESTATE = -5,      /* call not valid in the lattice's current state */
+    LBEM_ENOTFINITE = -6   /* non-finite media */
+} lbem_status;
+
+typedef enum { LBEM_MM = 0, LBEM_HV = 1 } lbem_model;
+
+/* Storage format of the populations.  Collision arithmetic is always FP32;
+ * BF16/FP16 only change how populations are held in HBM (round to nearest
+ * even on store).  FP16 multiplies by desc.storage_scale before rounding (and
+ * divides after loading) so that small fields stay in the normal range. */
+typedef enum { LBEM_F32 = 0, LBEM_BF16 = 1, LBEM_F16 = 2 } lbem_storage;
+
+typedef struct {
+    int32_t model;         /* lbem_model */
+    int32_t storage;       /* lbem_storage */
+    int32_t nx, ny, nz;    /* lattice size, each >= 1 */
+    int32_t reserved;      /* must be 0 */
+    double storage_scale;  /* FP16 only: power of two > 0 (0 means 1); ignored otherwise */
+} lbem_desc;
+
+typedef struct lbem_lattice lbem_lattice;
+
+/* Limits of the per-lattice tables held in the workspace. */
+#define LBEM_MAX_SOURCES 65536
+#define LBEM_MAX_PROBES 4096
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t lbem_version(void);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *lbem_last_error(void);
+
+/* Bytes of device workspace lbem_create needs for this descriptor. */
+lbem_status lbem_workspace_size(const lbem_desc *desc, size_t *bytes);
+
+/* Bytes of one population state (what save_state writes). */
+lbem_status lbem_state_size(const lbem_desc *desc, size_t *bytes);
+
+/* Create a lattice.
+ *   eps_r, mu_r, sigma: dev float [N] relative permittivity, relative
+ *       permeability and conductivity (in the model's own units, Sections I-B
+ *       and II-III); NULL means 1, 1 and 0.  They are copied into the workspace,
+ *       so the caller may free them after the call returns.
+ *   workspace: dev, >= lbem_workspace_size bytes, 256-byte aligned.
+ *   stream: a hipStream_t (NULL = the null stream).
+ * Validation (this call synchronises the stream once): every value finite
+ * (else LBEM_ENOTFINITE), eps_r > 0, mu_r > 0, sigma >= 0 (else LBEM_EINVAL),
+ * eps_r * mu_r >= 1 (else LBEM_EUNSTABLE: the wave would exceed the model's
+ * vacuum speed, which the paper states is unstable), and for HV
+ * sigma / (3 eps_r) < 2 (its explicit ohmic current is unstable beyond).
+ * The populations start at zero (no field) at time level 0. */
+lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *mu_r, const float *sigma,
+                        void *workspace, size_t workspace_bytes, void *stream, lbem_lattice **out);
+
+lbem_status lbem_destroy(lbem_lattice *lat);
+
+/* Change the stream later work is enqueued on. */
+lbem_status lbem_set_stream(lbem_lattice *lat, void *stream);
+
+/* Initialise every cell to the equilibrium of the given fields (Appendix B,
+ * first two lines): f = f_eq(E, B, J = 0), with rho_c = 0 for MM and D = eps E
+ * for HV.  E, B: dev float [3][N].  Resets the time level to 0. */
+lbem_status lbem_set_fields(lbem_lattice *lat, const float *E, const float *B);
+
+/* Soft current source (Section IV-C, Appendix B note): at time level n the
+ * cells get J_src = J0[k] sin(2 pi n / period + phase), which enters the
+ * current of eq. (MacorscopicCurrentMiller) for MM and the source term of eq.
+ * (SourceTermHV) for HV.  cells: host int64 [n] distinct cell indices; J0:
+ * host float [n][3].  n = 0 removes the source.  n <= LBEM_MAX_SOURCES,
+ * period > 0.  Synchronises the stream. */
+lbem_status lbem_set_current_source(lbem_lattice *lat, int32_t n, const int64_t *cells, const float *J0,
+                                    double period, double phase);
+
+/* Hard plane source (Appendix B "impose fields"): after the collision of step
+ * n, every cell of the plane z gets f' = f_eq(E_imp, B_imp, J = 0) with
+ * E_imp = E0 sin(2 pi n / period), B_imp = B0 sin(2 pi n / period).
+ * E0, B0: host float [3].  z < 0 removes the source. */
+lbem_status lbem_set_plane_source(lbem_lattice *lat, int32_t z, const float *E0, const float *B0, double period);
+
+/* Probe series: every later step records E and B of the state it collides
+ * (the fields reported at that time level) at the given cells into
+ * series[row][k][0..5] = (Ex, Ey, Ez, Bx, By, Bz), FP64, with
+ * row = (n - n_set) mod cap_rows where n_set is the time level at this call.
+ * cells: host int64 [n]; series: dev double [cap_rows][n][6].  n = 0 disables.
+ * Synchronises the stream. */
+lbem_status lbem_set_probes(lbem_lattice *lat, int32_t n, const int64_t *cells, int64_t cap_rows, double *series);
+
+/* Detector plane z (z < 0 disables): every later step adds the sum over the
+ * plane of |E|^2 of the state it collides to an FP64 accumulator kept in the
+ * workspace (deterministic order).  Setting the plane clears the accumulator. */
+lbem_status lbem_set_detector(lbem_lattice *lat, int32_t z);
+/* Write the accumulated detector sum to out (dev double [1]). */
+lbem_status lbem_detector_read(lbem_lattice *lat, double *out);
+
+/* Energy series: every later step whose time level n satisfies
+ * (n - n_set) mod every == 0 writes U = 1/2 sum (E.D + B.H) of the state it
+ * collides (FP64) to series[((n - n_set) / every) mod cap].  every <= 0 disables. */
+lbem_status lbem_set_energy_series(lbem_lattice *lat, int32_t every, int64_t cap, double *series);
+
+/* Advance nsteps time steps (asynchronous). */
+lbem_status lbem_step(lbem_lattice *lat, int64_t nsteps);
+
+/* Current time level. */
+lbem_status lbem_get_time(lbem_lattice *lat, int64_t *t);
+
+/* Reported fields of the current state (the pre-collision moments at the
+ * current time level; MM's E is the corrected field of eq. MacroscopicEMiller
+ * including the soft source at this time level).  Each of E, B, D, H is a dev
+ * float [3][N] or NULL to skip.  MM: D = eps_r E, H = B / (mu0 mu_r);
+ * HV: D and B are the moments, E = D / (eps0 eps_r), H = B / (mu0 mu_r). */
+lbem_status lbem_get_fields(lbem_lattice *lat, float *E, float *B, float *D, float *H);
+
+/* U = 1/2 sum over cells of (E.D + B.H) of the current state -> out (dev double [1]). */
+lbem_status lbem_energy(lbem_lattice *lat, double *out);
+
+/* Copy the population state to dst (dev, lbem_state_size bytes) / restore it
+ * together with the time level it was saved at (get it with lbem_get_time). */
+lbem_status lbem_save_state(lbem_lattice *lat, void *dst);
+lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBEM_H */

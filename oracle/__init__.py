@@ -54,6 +54,7 @@ def _lib(real: str = "f64"):
         lib = C.CDLL(path)
         P = C.c_void_p
         lib.oracle_real_bytes.restype = C.c_int
+        lib.oracle_threads.restype = C.c_int
         lib.oracle_nq.argtypes = [C.c_int]
         lib.oracle_velocity.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_mm_tables.argtypes = [P, P, P]
@@ -201,6 +202,11 @@ def fields(prob: Problem, f: np.ndarray, n: int):
     if rc != 0:
         raise ValueError("oracle_fields rejected the problem")
     return tuple(outs)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle runs with."""
+    return int(_lib().oracle_threads())
 
 
 # ---------------------------------------------------------------- single cell

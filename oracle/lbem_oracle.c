@@ -41,6 +41,7 @@
  *   - Time dependent sources use the time level n of the state being collided.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -201,6 +202,7 @@ static void hv_source(const real J[3], real T[6][3]) {
 /* Exported single-cell operators (used by the identity and spectral tests)  */
 
 int oracle_real_bytes(void) { return (int)sizeof(real); }
+int oracle_threads(void) { return omp_get_max_threads(); }
 int oracle_nq(int model) { return model == MODEL_MM ? MM_Q : (model == MODEL_HV ? HV_Q : -1); }
 
 /* velocity of population q (integer components), for either model */

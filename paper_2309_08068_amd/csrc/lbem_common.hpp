@@ -1,0 +1,124 @@
+// lbem_common.hpp -- storage formats, neighbour addressing and block reductions
+// shared by the step, observation and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbem_model.hpp"
+
+namespace lbem {
+
+constexpr int kBlock = 256;  // threads per block of the lattice kernels (4 waves)
+
+// ------------------------------------------------------------ storage formats
+// Populations live in HBM as FP32, BF16 or FP16; collision math is FP32.
+struct StF32 {
+    using T = float;
+    static constexpr int kBytes = 4;
+    __device__ static float load(const T *p, uint32_t i, float) { return p[i]; }
+    __device__ static void store(T *p, uint32_t i, float v, float) { p[i] = v; }
+};
+
+struct StBF16 {
+    using T = uint16_t;
+    static constexpr int kBytes = 2;
+    __device__ static float load(const T *p, uint32_t i, float) { return __uint_as_float(uint32_t(p[i]) << 16); }
+    // round to nearest, ties to even (inputs are finite)
+    __device__ static uint16_t pack(float v) {
+        uint32_t u = __float_as_uint(v);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return uint16_t(u >> 16);
+    }
+    __device__ static void store(T *p, uint32_t i, float v, float) { p[i] = pack(v); }
+};
+
+struct StF16 {
+    using T = _Float16;
+    static constexpr int kBytes = 2;
+    // values are held multiplied by a power-of-two scale
+    __device__ static float load(const T *p, uint32_t i, float inv_scale) { return float(p[i]) * inv_scale; }
+    __device__ static void store(T *p, uint32_t i, float v, float scale) { p[i] = _Float16(v * scale); }
+};
+
+// ------------------------------------------------------------ addressing
+// Periodic neighbours of one cell: coordinates of x-1, x, x+1 and the row
+// offsets of y-1, y, y+1 and z-1, z, z+1.
+struct Nbr {
+    uint32_t c;
+    uint32_t xs[3];
+    uint32_t ys[3];
+    uint32_t zs[3];
+    __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const {
+        return xs[dx + 1] + ys[dy + 1] + zs[dz + 1];
+    }
+};
+
+__device__ __forceinline__ Nbr make_nbr(uint32_t c, uint32_t x, uint32_t y, uint32_t z, uint32_t nx, uint32_t ny,
+                                        uint32_t nz) {
+    Nbr n;
+    n.c = c;
+    const uint32_t nxy = nx * ny;
+    n.xs[0] = x == 0 ? nx - 1 : x - 1;
+    n.xs[1] = x;
+    n.xs[2] = x + 1 == nx ? 0 : x + 1;
+    n.ys[0] = (y == 0 ? ny - 1 : y - 1) * nx;
+    n.ys[1] = y * nx;
+    n.ys[2] = (y + 1 == ny ? 0 : y + 1) * nx;
+    n.zs[0] = (z == 0 ? nz - 1 : z - 1) * nxy;
+    n.zs[1] = z * nxy;
+    n.zs[2] = (z + 1 == nz ? 0 : z + 1) * nxy;
+    return n;
+}
+
+// In-place AA streaming.  The array holds, before the step at time level t:
+//   t even: slot (q, x) = population q at x (natural layout);
+//   t odd:  slot (opp q, x - v_q) = population q arriving at x (it is the
+//           post-collision value that x - v_q wrote during the previous step).
+// The step at an even t writes f'_q(x) to slot (opp q, x); at an odd t it
+// writes f'_q(x) to slot (q, x + v_q).  Each cell reads exactly the slots it
+// later writes, so the update is race-free without a second array.
+template <class M, int ODD, class ST>
+__device__ __forceinline__ void gather(const typename ST::T *__restrict__ pop, size_t N, const Nbr &nb,
+                                       float (&f)[M::Q], float inv_scale) {
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) {
+        if (ODD) {
+            const uint32_t i = nb.at(-M::vel(q, 0), -M::vel(q, 1), -M::vel(q, 2));
+            f[q] = ST::load(pop + size_t(M::opp(q)) * N, i, inv_scale);
+        } else {
+            f[q] = ST::load(pop + size_t(q) * N, nb.c, inv_scale);
+        }
+    }
+}
+
+template <class M, int ODD, class ST>
+__device__ __forceinline__ void scatter(typename ST::T *__restrict__ pop, size_t N, const Nbr &nb,
+                                        const float (&f)[M::Q], float scale) {
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) {
+        if (ODD) {
+            const uint32_t i = nb.at(M::vel(q, 0), M::vel(q, 1), M::vel(q, 2));
+            ST::store(pop + size_t(q) * N, i, f[q], scale);
+        } else {
+            ST::store(pop + size_t(M::opp(q)) * N, nb.c, f[q], scale);
+        }
+    }
+}
+
+// ------------------------------------------------------------ reductions
+// Sum of one double per thread over a block of kBlock threads, in a fixed
+// order (wavefront butterfly, then the four wave partials in order).  The
+// result is valid in thread 0.  `sm` is a __shared__ double[4].
+__device__ __forceinline__ double block_sum(double v, double *sm) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sm[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+    return r;
+}
+
+}  // namespace lbem

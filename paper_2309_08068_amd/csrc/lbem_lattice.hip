@@ -1,0 +1,757 @@
+// lbem_lattice.hip -- kernels and C ABI of the 3-D lattice (include/lbem.h).
+//
+// One kernel launch performs one complete time step of Appendix B for every
+// cell: gather the populations (in-place AA streaming), collide (Section II or
+// III), impose hard sources, scatter, and -- when requested for this step --
+// record probes, the detector-plane |E|^2 and per-block energy partials in
+// FP64.  One thread owns one cell; cells are numbered x fastest so every
+// population plane is read and written in contiguous 256-cell runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbem.h"
+#include "lbem_common.hpp"
+#include "lbem_internal.hpp"
+
+using namespace lbem;
+
+// ============================================================== kernels
+
+struct StepArgs {
+    void *pop;
+    const float *eps, *mu, *sig;
+    uint32_t nx, ny, nz, N;
+    float scale, inv_scale;
+    // soft current source: per-block ranges into a cell-sorted list
+    const int32_t *src_blk, *src_cell;
+    const float *src_J0;
+    float src_w;
+    // hard plane source
+    int32_t plane_z;
+    float Eimp[3], Bimp[3];
+    // probes: per-block ranges, cell, output slot; prb_row = this step's row
+    const int32_t *prb_blk, *prb_cell, *prb_slot;
+    double *prb_row;
+    // detector plane
+    int32_t det_z;
+    uint32_t det_b0, det_b1;
+    double *det_part;
+    // energy partials (null: not this step)
+    double *en_part;
+};
+
+template <class M, int ODD, class ST>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
+    __shared__ double sm_en[4], sm_det[4];
+    const uint32_t blk = blockIdx.x;
+    const uint32_t c = blk * kBlock + threadIdx.x;
+    const bool live = c < a.N;
+    const uint32_t cc = live ? c : a.N - 1;
+    const uint32_t nxy = a.nx * a.ny;
+    const uint32_t z = cc / nxy, rem = cc - z * nxy, y = rem / a.nx, x = rem - y * a.nx;
+    const Nbr nb = make_nbr(cc, x, y, z, a.nx, a.ny, a.nz);
+    const size_t N = a.N;
+    auto *pop = static_cast<typename ST::T *>(a.pop);
+
+    float f[M::Q];
+    if (live) gather<M, ODD, ST>(pop, N, nb, f, a.inv_scale);
+    else
+        for (int q = 0; q < M::Q; ++q) f[q] = 0.f;
+
+    CellMedia m{a.eps[cc], a.mu[cc], a.sig[cc]};
+    float Js[3] = {0.f, 0.f, 0.f};
+    if (a.src_blk) {
+        const int s0 = a.src_blk[blk], s1 = a.src_blk[blk + 1];
+        for (int k = s0; k < s1; ++k)
+            if (a.src_cell[k] == int32_t(c)) {
+                Js[0] = a.src_J0[3 * k] * a.src_w;
+                Js[1] = a.src_J0[3 * k + 1] * a.src_w;
+                Js[2] = a.src_J0[3 * k + 2] * a.src_w;
+            }
+    }
+    CellFields o;
+    Cell<M>::collide(f, m, Js, o);
+    if (int32_t(z) == a.plane_z) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
+    if (live) scatter<M, ODD, ST>(pop, N, nb, f, a.scale);
+
+    // ---- observation of the state this step collided
+    if (a.prb_blk) {
+        const int p0 = a.prb_blk[blk], p1 = a.prb_blk[blk + 1];
+        for (int k = p0; k < p1; ++k)
+            if (a.prb_cell[k] == int32_t(c)) {
+                double *o6 = a.prb_row + 6 * a.prb_slot[k];
+                o6[0] = o.E[0]; o6[1] = o.E[1]; o6[2] = o.E[2];
+                o6[3] = o.B[0]; o6[4] = o.B[1]; o6[5] = o.B[2];
+            }
+    }
+    if (a.det_part && blk >= a.det_b0 && blk <= a.det_b1) {
+        const double e2 = (live && int32_t(z) == a.det_z)
+                              ? double(o.E[0]) * o.E[0] + double(o.E[1]) * o.E[1] + double(o.E[2]) * o.E[2]
+                              : 0.0;
+        const double s = block_sum(e2, sm_det);
+        if (threadIdx.x == 0) a.det_part[blk - a.det_b0] += s;
+    }
+    if (a.en_part) {
+        const double u = live ? 0.5 * (double(o.E[0]) * o.D[0] + double(o.E[1]) * o.D[1] + double(o.E[2]) * o.D[2] +
+                                       double(o.B[0]) * o.H[0] + double(o.B[1]) * o.H[1] + double(o.B[2]) * o.H[2])
+                              : 0.0;
+        const double s = block_sum(u, sm_en);
+        if (threadIdx.x == 0) a.en_part[blk] = s;
+    }
+}
+
+struct ObsArgs {
+    const void *pop;
+    const float *eps, *mu, *sig;
+    uint32_t nx, ny, nz, N;
+    float inv_scale;
+    const int32_t *src_blk, *src_cell;
+    const float *src_J0;
+    float src_w;
+    float *E, *B, *D, *H;
+    double *en_part;
+};
+
+// Reported fields of the current state (no update).
+template <class M, int ODD, class ST>
+__global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
+    __shared__ double sm_en[4];
+    const uint32_t blk = blockIdx.x;
+    const uint32_t c = blk * kBlock + threadIdx.x;
+    const bool live = c < a.N;
+    const uint32_t cc = live ? c : a.N - 1;
+    const uint32_t nxy = a.nx * a.ny;
+    const uint32_t z = cc / nxy, rem = cc - z * nxy, y = rem / a.nx, x = rem - y * a.nx;
+    const Nbr nb = make_nbr(cc, x, y, z, a.nx, a.ny, a.nz);
+    const size_t N = a.N;
+    float f[M::Q];
+    gather<M, ODD, ST>(static_cast<const typename ST::T *>(a.pop), N, nb, f, a.inv_scale);
+    CellMedia m{a.eps[cc], a.mu[cc], a.sig[cc]};
+    float Js[3] = {0.f, 0.f, 0.f};
+    if (a.src_blk) {
+        const int s0 = a.src_blk[blk], s1 = a.src_blk[blk + 1];
+        for (int k = s0; k < s1; ++k)
+            if (a.src_cell[k] == int32_t(c)) {
+                Js[0] = a.src_J0[3 * k] * a.src_w;
+                Js[1] = a.src_J0[3 * k + 1] * a.src_w;
+                Js[2] = a.src_J0[3 * k + 2] * a.src_w;
+            }
+    }
+    CellFields o;
+    Cell<M>::collide(f, m, Js, o);
+    if (live) {
+        for (int d = 0; d < 3; ++d) {
+            if (a.E) a.E[d * N + c] = o.E[d];
+            if (a.B) a.B[d * N + c] = o.B[d];
+            if (a.D) a.D[d * N + c] = o.D[d];
+            if (a.H) a.H[d * N + c] = o.H[d];
+        }
+    }
+    if (a.en_part) {
+        const double u = live ? 0.5 * (double(o.E[0]) * o.D[0] + double(o.E[1]) * o.D[1] + double(o.E[2]) * o.D[2] +
+                                       double(o.B[0]) * o.H[0] + double(o.B[1]) * o.H[1] + double(o.B[2]) * o.H[2])
+                              : 0.0;
+        const double s = block_sum(u, sm_en);
+        if (threadIdx.x == 0) a.en_part[blk] = s;
+    }
+}
+
+// f := f_eq(E, B, J = 0) in natural layout.
+template <class M, class ST>
+__global__ __launch_bounds__(kBlock) void init_kernel(void *pop, const float *eps, const float *mu, const float *E,
+                                                      const float *B, uint32_t N, float scale) {
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= N) return;
+    CellMedia m{eps[c], mu[c], 0.f};
+    const float e[3] = {E[c], E[size_t(N) + c], E[2 * size_t(N) + c]};
+    const float b[3] = {B[c], B[size_t(N) + c], B[2 * size_t(N) + c]};
+    float f[M::Q];
+    Cell<M>::equilibrium(f, m, e, b);
+    auto *p = static_cast<typename ST::T *>(pop);
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) ST::store(p + size_t(q) * N, c, f[q], scale);
+}
+
+// Fill a float array with a value, or copy src into it.
+__global__ void fill_or_copy(float *dst, const float *src, float value, uint32_t N) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < N) dst[i] = src ? src[i] : value;
+}
+
+__global__ void zero_bytes(uint32_t *dst, size_t nwords) {
+    const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < nwords) dst[i] = 0u;
+}
+
+// counts[0] non-finite, [1] non-positive eps/mu or negative sigma,
+// [2] eps mu < 1, [3] HV sigma / (3 eps) >= 2
+__global__ void validate_media(const float *eps, const float *mu, const float *sig, uint32_t N, int model,
+                               int32_t *counts) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    const float e = eps[i], m = mu[i], s = sig[i];
+    if (!isfinite(e) || !isfinite(m) || !isfinite(s)) {
+        atomicAdd(&counts[0], 1);
+        return;
+    }
+    if (!(e > 0.f) || !(m > 0.f) || s < 0.f) atomicAdd(&counts[1], 1);
+    else if (double(e) * double(m) < 1.0 - 1e-6) atomicAdd(&counts[2], 1);
+    if (model == LBEM_HV && s / (3.0f * e) >= 2.0f) atomicAdd(&counts[3], 1);
+}
+
+// Deterministic sum of n partials into out[0] (one block).
+__global__ __launch_bounds__(kBlock) void sum_partials(const double *part, uint32_t n, double *out) {
+    __shared__ double sm[4];
+    double s = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) s += part[i];
+    s = block_sum(s, sm);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+// ============================================================== host side
+
+namespace lbem {
+thread_local char g_err[512] = "";
+
+lbem_status fail(lbem_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+lbem_status hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return LBEM_OK;
+    return fail(LBEM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+}  // namespace lbem
+
+struct lbem_lattice {
+    lbem_desc d;
+    int Q;
+    size_t sbytes;
+    uint32_t N, nblocks;
+    float scale, inv_scale;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    WsLayout L;
+    // sources
+    int32_t nsrc;
+    double src_period, src_phase;
+    int32_t plane_z;
+    float pE0[3], pB0[3];
+    double plane_period;
+    // probes
+    int32_t nprobe;
+    int64_t prb_cap, prb_t0;
+    double *prb_series;
+    // detector
+    int32_t det_z;
+    uint32_t det_b0, det_b1;
+    // energy series
+    int32_t en_every;
+    int64_t en_cap, en_t0;
+    double *en_series;
+    int64_t t;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+lbem_status check_desc(const lbem_desc *d) {
+    if (!d) return fail(LBEM_EINVAL, "desc is NULL");
+    if (d->model != LBEM_MM && d->model != LBEM_HV) return fail(LBEM_EINVAL, "unknown model %d", d->model);
+    if (d->storage < LBEM_F32 || d->storage > LBEM_F16) return fail(LBEM_EINVAL, "unknown storage %d", d->storage);
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(LBEM_EINVAL, "lattice size must be >= 1 on every axis");
+    if (d->reserved != 0) return fail(LBEM_EINVAL, "reserved field must be 0");
+    const double n = double(d->nx) * d->ny * d->nz;
+    if (n >= 2147483648.0) return fail(LBEM_EINVAL, "lattice has %.0f cells; the limit is 2^31 - 1", n);
+    if (d->storage == LBEM_F16 && d->storage_scale != 0.0) {
+        int ex;
+        const double m = std::frexp(d->storage_scale, &ex);
+        if (!(d->storage_scale > 0.0) || m != 0.5) return fail(LBEM_EINVAL, "storage_scale must be a power of two");
+    }
+    return LBEM_OK;
+}
+
+int model_q(int model) { return model == LBEM_MM ? 50 : 36; }
+size_t storage_bytes(int st) { return st == LBEM_F32 ? 4 : 2; }
+
+}  // namespace
+
+namespace lbem {
+WsLayout layout(const lbem_desc *d) {
+    WsLayout L;
+    const size_t N = size_t(d->nx) * d->ny * d->nz;
+    const size_t nblocks = (N + kBlock - 1) / kBlock;
+    const size_t nxy = size_t(d->nx) * d->ny;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.pop = take(N * model_q(d->model) * storage_bytes(d->storage));
+    L.eps = take(N * 4);
+    L.mu = take(N * 4);
+    L.sig = take(N * 4);
+    L.en_part = take(nblocks * 8);
+    L.det_cap = nxy / kBlock + 2;
+    L.det_part = take(L.det_cap * 8);
+    L.src_blk = take((nblocks + 1) * 4);
+    L.src_cell = take(size_t(LBEM_MAX_SOURCES) * 4);
+    L.src_J0 = take(size_t(LBEM_MAX_SOURCES) * 12);
+    L.prb_blk = take((nblocks + 1) * 4);
+    L.prb_cell = take(size_t(LBEM_MAX_PROBES) * 4);
+    L.prb_slot = take(size_t(LBEM_MAX_PROBES) * 4);
+    L.flags = take(64);
+    L.total = off;
+    return L;
+}
+}  // namespace lbem
+
+// The exported functions below get C linkage from their declarations in lbem.h.
+
+int32_t lbem_version(void) { return 10000; }
+
+const char *lbem_last_error(void) { return g_err; }
+
+lbem_status lbem_workspace_size(const lbem_desc *desc, size_t *bytes) {
+    lbem_status st = check_desc(desc);
+    if (st) return st;
+    if (!bytes) return fail(LBEM_EINVAL, "bytes is NULL");
+    *bytes = layout(desc).total;
+    return LBEM_OK;
+}
+
+lbem_status lbem_state_size(const lbem_desc *desc, size_t *bytes) {
+    lbem_status st = check_desc(desc);
+    if (st) return st;
+    if (!bytes) return fail(LBEM_EINVAL, "bytes is NULL");
+    *bytes = size_t(desc->nx) * desc->ny * desc->nz * model_q(desc->model) * storage_bytes(desc->storage);
+    return LBEM_OK;
+}
+
+static uint32_t grid_for(size_t n) { return uint32_t((n + kBlock - 1) / kBlock); }
+
+lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *mu_r, const float *sigma,
+                        void *workspace, size_t workspace_bytes, void *stream, lbem_lattice **out) {
+    lbem_status st = check_desc(desc);
+    if (st) return st;
+    if (!out) return fail(LBEM_EINVAL, "out is NULL");
+    if (!workspace) return fail(LBEM_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(LBEM_EINVAL, "workspace must be 256-byte aligned");
+    WsLayout L = layout(desc);
+    if (workspace_bytes < L.total)
+        return fail(LBEM_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    auto *lat = new (std::nothrow) lbem_lattice();
+    if (!lat) return fail(LBEM_ENOMEM, "host allocation failed");
+    lat->d = *desc;
+    lat->Q = model_q(desc->model);
+    lat->sbytes = storage_bytes(desc->storage);
+    lat->N = uint32_t(size_t(desc->nx) * desc->ny * desc->nz);
+    lat->nblocks = grid_for(lat->N);
+    lat->scale = (desc->storage == LBEM_F16 && desc->storage_scale != 0.0) ? float(desc->storage_scale) : 1.0f;
+    lat->inv_scale = 1.0f / lat->scale;
+    lat->stream = static_cast<hipStream_t>(stream);
+    lat->ws = static_cast<char *>(workspace);
+    lat->ws_bytes = workspace_bytes;
+    lat->L = L;
+    lat->plane_z = -1;
+    lat->det_z = -1;
+    lat->t = 0;
+    hipStream_t s = lat->stream;
+    float *eps = reinterpret_cast<float *>(lat->ws + L.eps);
+    float *mu = reinterpret_cast<float *>(lat->ws + L.mu);
+    float *sig = reinterpret_cast<float *>(lat->ws + L.sig);
+    const uint32_t g = grid_for(lat->N);
+    hipLaunchKernelGGL(fill_or_copy, dim3(g), dim3(kBlock), 0, s, eps, eps_r, 1.0f, lat->N);
+    hipLaunchKernelGGL(fill_or_copy, dim3(g), dim3(kBlock), 0, s, mu, mu_r, 1.0f, lat->N);
+    hipLaunchKernelGGL(fill_or_copy, dim3(g), dim3(kBlock), 0, s, sig, sigma, 0.0f, lat->N);
+    // zero everything after the media (partials, tables, flags) and the populations
+    const size_t tail = L.total - L.en_part;
+    hipLaunchKernelGGL(zero_bytes, dim3(grid_for(tail / 4)), dim3(kBlock), 0, s,
+                       reinterpret_cast<uint32_t *>(lat->ws + L.en_part), tail / 4);
+    const size_t popw = size_t(lat->N) * lat->Q * lat->sbytes / 4;
+    hipLaunchKernelGGL(zero_bytes, dim3(grid_for(popw)), dim3(kBlock), 0, s,
+                       reinterpret_cast<uint32_t *>(lat->ws + L.pop), popw);
+    int32_t *flags = reinterpret_cast<int32_t *>(lat->ws + L.flags);
+    hipLaunchKernelGGL(validate_media, dim3(g), dim3(kBlock), 0, s, eps, mu, sig, lat->N, desc->model, flags);
+    int32_t counts[4] = {0, 0, 0, 0};
+    st = hip_check(hipGetLastError(), "launch");
+    if (!st) st = hip_check(hipMemcpyAsync(counts, flags, sizeof(counts), hipMemcpyDeviceToHost, s), "copy flags");
+    if (!st) st = hip_check(hipStreamSynchronize(s), "synchronise");
+    if (!st && counts[0]) st = fail(LBEM_ENOTFINITE, "%d cells have non-finite media", counts[0]);
+    if (!st && counts[1]) st = fail(LBEM_EINVAL, "%d cells have eps_r <= 0, mu_r <= 0 or sigma < 0", counts[1]);
+    if (!st && counts[2])
+        st = fail(LBEM_EUNSTABLE, "%d cells have eps_r * mu_r < 1 (faster than the vacuum speed)", counts[2]);
+    if (!st && counts[3]) st = fail(LBEM_EUNSTABLE, "%d cells have sigma / (3 eps_r) >= 2 (HV current)", counts[3]);
+    if (st) {
+        delete lat;
+        return st;
+    }
+    *out = lat;
+    return LBEM_OK;
+}
+
+lbem_status lbem_destroy(lbem_lattice *lat) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    delete lat;
+    return LBEM_OK;
+}
+
+lbem_status lbem_set_stream(lbem_lattice *lat, void *stream) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    lat->stream = static_cast<hipStream_t>(stream);
+    return LBEM_OK;
+}
+
+template <class M, class ST>
+static void launch_init(lbem_lattice *lat, const float *E, const float *B) {
+    hipLaunchKernelGGL((init_kernel<M, ST>), dim3(lat->nblocks), dim3(kBlock), 0, lat->stream, lat->ws + lat->L.pop,
+                       reinterpret_cast<const float *>(lat->ws + lat->L.eps),
+                       reinterpret_cast<const float *>(lat->ws + lat->L.mu), E, B, lat->N, lat->scale);
+}
+
+template <class M>
+static void dispatch_init(lbem_lattice *lat, const float *E, const float *B) {
+    switch (lat->d.storage) {
+        case LBEM_F32: launch_init<M, StF32>(lat, E, B); break;
+        case LBEM_BF16: launch_init<M, StBF16>(lat, E, B); break;
+        default: launch_init<M, StF16>(lat, E, B); break;
+    }
+}
+
+lbem_status lbem_set_fields(lbem_lattice *lat, const float *E, const float *B) {
+    if (!lat || !E || !B) return fail(LBEM_EINVAL, "null argument");
+    if (lat->d.model == LBEM_MM) dispatch_init<MM>(lat, E, B);
+    else dispatch_init<HV>(lat, E, B);
+    lat->t = 0;
+    return hip_check(hipGetLastError(), "init launch");
+}
+
+// Build per-block [start, end) ranges into a cell-sorted list.
+static std::vector<int32_t> block_ranges(const std::vector<int32_t> &sorted_cells, uint32_t nblocks) {
+    std::vector<int32_t> r(nblocks + 1);
+    size_t k = 0;
+    for (uint32_t b = 0; b <= nblocks; ++b) {
+        const int64_t first = int64_t(b) * kBlock;
+        while (k < sorted_cells.size() && sorted_cells[k] < first) ++k;
+        r[b] = int32_t(k);
+    }
+    return r;
+}
+
+lbem_status lbem_set_current_source(lbem_lattice *lat, int32_t n, const int64_t *cells, const float *J0,
+                                    double period, double phase) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (n < 0 || n > LBEM_MAX_SOURCES) return fail(LBEM_EINVAL, "source count %d outside [0, %d]", n, LBEM_MAX_SOURCES);
+    if (n == 0) {
+        lat->nsrc = 0;
+        return LBEM_OK;
+    }
+    if (!cells || !J0) return fail(LBEM_EINVAL, "null source arrays");
+    if (!(period > 0.0) || !std::isfinite(period) || !std::isfinite(phase))
+        return fail(LBEM_EINVAL, "period must be finite and > 0");
+    std::vector<int32_t> order(n);
+    for (int32_t k = 0; k < n; ++k) {
+        if (cells[k] < 0 || cells[k] >= int64_t(lat->N)) return fail(LBEM_EINVAL, "source cell %lld out of range", (long long)cells[k]);
+        if (!std::isfinite(J0[3 * k]) || !std::isfinite(J0[3 * k + 1]) || !std::isfinite(J0[3 * k + 2]))
+            return fail(LBEM_ENOTFINITE, "source amplitude %d is not finite", k);
+        order[k] = k;
+    }
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cells[a] < cells[b]; });
+    std::vector<int32_t> sc(n);
+    std::vector<float> sj(3 * size_t(n));
+    for (int32_t k = 0; k < n; ++k) {
+        sc[k] = int32_t(cells[order[k]]);
+        if (k && sc[k] == sc[k - 1]) return fail(LBEM_EINVAL, "source cell %d repeated", sc[k]);
+        for (int a = 0; a < 3; ++a) sj[3 * k + a] = J0[3 * order[k] + a];
+    }
+    std::vector<int32_t> br = block_ranges(sc, lat->nblocks);
+    hipStream_t s = lat->stream;
+    lbem_status st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_blk, br.data(), br.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_cell, sc.data(), sc.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_J0, sj.data(), sj.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipStreamSynchronize(s), "synchronise");
+    if (st) return st;
+    lat->nsrc = n;
+    lat->src_period = period;
+    lat->src_phase = phase;
+    return LBEM_OK;
+}
+
+lbem_status lbem_set_plane_source(lbem_lattice *lat, int32_t z, const float *E0, const float *B0, double period) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (z < 0) {
+        lat->plane_z = -1;
+        return LBEM_OK;
+    }
+    if (z >= lat->d.nz) return fail(LBEM_EINVAL, "plane z = %d outside the lattice", z);
+    if (!E0 || !B0) return fail(LBEM_EINVAL, "null source vectors");
+    if (!(period > 0.0) || !std::isfinite(period)) return fail(LBEM_EINVAL, "period must be finite and > 0");
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(E0[a]) || !std::isfinite(B0[a])) return fail(LBEM_ENOTFINITE, "source vector not finite");
+        lat->pE0[a] = E0[a];
+        lat->pB0[a] = B0[a];
+    }
+    lat->plane_z = z;
+    lat->plane_period = period;
+    return LBEM_OK;
+}
+
+lbem_status lbem_set_probes(lbem_lattice *lat, int32_t n, const int64_t *cells, int64_t cap_rows, double *series) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (n < 0 || n > LBEM_MAX_PROBES) return fail(LBEM_EINVAL, "probe count %d outside [0, %d]", n, LBEM_MAX_PROBES);
+    if (n == 0) {
+        lat->nprobe = 0;
+        return LBEM_OK;
+    }
+    if (!cells || !series || cap_rows < 1) return fail(LBEM_EINVAL, "null probe arrays or cap_rows < 1");
+    std::vector<int32_t> order(n);
+    for (int32_t k = 0; k < n; ++k) {
+        if (cells[k] < 0 || cells[k] >= int64_t(lat->N)) return fail(LBEM_EINVAL, "probe cell %lld out of range", (long long)cells[k]);
+        order[k] = k;
+    }
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cells[a] < cells[b]; });
+    std::vector<int32_t> pc(n), ps(n);
+    for (int32_t k = 0; k < n; ++k) {
+        pc[k] = int32_t(cells[order[k]]);
+        ps[k] = order[k];
+    }
+    std::vector<int32_t> br = block_ranges(pc, lat->nblocks);
+    hipStream_t s = lat->stream;
+    lbem_status st = hip_check(hipMemcpyAsync(lat->ws + lat->L.prb_blk, br.data(), br.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.prb_cell, pc.data(), pc.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.prb_slot, ps.data(), ps.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipStreamSynchronize(s), "synchronise");
+    if (st) return st;
+    lat->nprobe = n;
+    lat->prb_cap = cap_rows;
+    lat->prb_t0 = lat->t;
+    lat->prb_series = series;
+    return LBEM_OK;
+}
+
+lbem_status lbem_set_detector(lbem_lattice *lat, int32_t z) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (z >= lat->d.nz) return fail(LBEM_EINVAL, "detector z = %d outside the lattice", z);
+    if (z < 0) {
+        lat->det_z = -1;
+        return LBEM_OK;
+    }
+    const uint64_t nxy = uint64_t(lat->d.nx) * lat->d.ny;
+    lat->det_z = z;
+    lat->det_b0 = uint32_t((uint64_t(z) * nxy) / kBlock);
+    lat->det_b1 = uint32_t((uint64_t(z + 1) * nxy - 1) / kBlock);
+    const size_t words = size_t(lat->L.det_cap) * 2;
+    hipLaunchKernelGGL(zero_bytes, dim3(grid_for(words)), dim3(kBlock), 0, lat->stream,
+                       reinterpret_cast<uint32_t *>(lat->ws + lat->L.det_part), words);
+    return hip_check(hipGetLastError(), "zero detector");
+}
+
+lbem_status lbem_detector_read(lbem_lattice *lat, double *out) {
+    if (!lat || !out) return fail(LBEM_EINVAL, "null argument");
+    if (lat->det_z < 0) return fail(LBEM_ESTATE, "no detector plane set");
+    hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream,
+                       reinterpret_cast<const double *>(lat->ws + lat->L.det_part), lat->det_b1 - lat->det_b0 + 1, out);
+    return hip_check(hipGetLastError(), "detector sum");
+}
+
+lbem_status lbem_set_energy_series(lbem_lattice *lat, int32_t every, int64_t cap, double *series) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (every <= 0) {
+        lat->en_every = 0;
+        return LBEM_OK;
+    }
+    if (!series || cap < 1) return fail(LBEM_EINVAL, "null energy series or cap < 1");
+    lat->en_every = every;
+    lat->en_cap = cap;
+    lat->en_t0 = lat->t;
+    lat->en_series = series;
+    return LBEM_OK;
+}
+
+template <class M, int ODD, class ST>
+static void launch_step(const StepArgs &a, uint32_t nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((step_kernel<M, ODD, ST>), dim3(nblocks), dim3(kBlock), 0, s, a);
+}
+
+template <class M, int ODD>
+static void dispatch_step_storage(const lbem_lattice *lat, const StepArgs &a) {
+    switch (lat->d.storage) {
+        case LBEM_F32: launch_step<M, ODD, StF32>(a, lat->nblocks, lat->stream); break;
+        case LBEM_BF16: launch_step<M, ODD, StBF16>(a, lat->nblocks, lat->stream); break;
+        default: launch_step<M, ODD, StF16>(a, lat->nblocks, lat->stream); break;
+    }
+}
+
+static void dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd) {
+    if (lat->d.model == LBEM_MM) {
+        if (odd) dispatch_step_storage<MM, 1>(lat, a);
+        else dispatch_step_storage<MM, 0>(lat, a);
+    } else {
+        if (odd) dispatch_step_storage<HV, 1>(lat, a);
+        else dispatch_step_storage<HV, 0>(lat, a);
+    }
+}
+
+namespace lbem {
+double two_pi_frac(double n, double period, double phase) {
+    // 2 pi n / period + phase, with the integer number of periods removed first
+    const double r = n / period;
+    return 2.0 * M_PI * (r - std::floor(r)) + phase;
+}
+}  // namespace lbem
+
+lbem_status lbem_step(lbem_lattice *lat, int64_t nsteps) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (nsteps < 0) return fail(LBEM_EINVAL, "nsteps < 0");
+    const WsLayout &L = lat->L;
+    StepArgs a{};
+    a.pop = lat->ws + L.pop;
+    a.eps = reinterpret_cast<const float *>(lat->ws + L.eps);
+    a.mu = reinterpret_cast<const float *>(lat->ws + L.mu);
+    a.sig = reinterpret_cast<const float *>(lat->ws + L.sig);
+    a.nx = lat->d.nx;
+    a.ny = lat->d.ny;
+    a.nz = lat->d.nz;
+    a.N = lat->N;
+    a.scale = lat->scale;
+    a.inv_scale = lat->inv_scale;
+    if (lat->nsrc > 0) {
+        a.src_blk = reinterpret_cast<const int32_t *>(lat->ws + L.src_blk);
+        a.src_cell = reinterpret_cast<const int32_t *>(lat->ws + L.src_cell);
+        a.src_J0 = reinterpret_cast<const float *>(lat->ws + L.src_J0);
+    }
+    a.plane_z = lat->plane_z;
+    if (lat->nprobe > 0) {
+        a.prb_blk = reinterpret_cast<const int32_t *>(lat->ws + L.prb_blk);
+        a.prb_cell = reinterpret_cast<const int32_t *>(lat->ws + L.prb_cell);
+        a.prb_slot = reinterpret_cast<const int32_t *>(lat->ws + L.prb_slot);
+    }
+    a.det_z = lat->det_z;
+    if (lat->det_z >= 0) {
+        a.det_b0 = lat->det_b0;
+        a.det_b1 = lat->det_b1;
+        a.det_part = reinterpret_cast<double *>(lat->ws + L.det_part);
+    }
+    double *en_part = reinterpret_cast<double *>(lat->ws + L.en_part);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int64_t t = lat->t;
+        if (lat->nsrc > 0) a.src_w = float(std::sin(two_pi_frac(double(t), lat->src_period, lat->src_phase)));
+        if (lat->plane_z >= 0) {
+            const double w = std::sin(two_pi_frac(double(t), lat->plane_period, 0.0));
+            for (int k = 0; k < 3; ++k) {
+                a.Eimp[k] = float(lat->pE0[k] * w);
+                a.Bimp[k] = float(lat->pB0[k] * w);
+            }
+        }
+        if (lat->nprobe > 0) a.prb_row = lat->prb_series + ((t - lat->prb_t0) % lat->prb_cap) * lat->nprobe * 6;
+        const bool en = lat->en_every > 0 && (t - lat->en_t0) % lat->en_every == 0;
+        a.en_part = en ? en_part : nullptr;
+        dispatch_step(lat, a, int(t & 1));
+        if (en) {
+            double *dst = lat->en_series + ((t - lat->en_t0) / lat->en_every) % lat->en_cap;
+            hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream, en_part, lat->nblocks, dst);
+        }
+        lbem_status st = hip_check(hipGetLastError(), "step launch");
+        if (st) return st;
+        lat->t = t + 1;
+    }
+    return LBEM_OK;
+}
+
+lbem_status lbem_get_time(lbem_lattice *lat, int64_t *t) {
+    if (!lat || !t) return fail(LBEM_EINVAL, "null argument");
+    *t = lat->t;
+    return LBEM_OK;
+}
+
+template <class M, int ODD, class ST>
+static void launch_obs(const ObsArgs &a, uint32_t nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((observe_kernel<M, ODD, ST>), dim3(nblocks), dim3(kBlock), 0, s, a);
+}
+template <class M, int ODD>
+static void dispatch_obs_storage(const lbem_lattice *lat, const ObsArgs &a) {
+    switch (lat->d.storage) {
+        case LBEM_F32: launch_obs<M, ODD, StF32>(a, lat->nblocks, lat->stream); break;
+        case LBEM_BF16: launch_obs<M, ODD, StBF16>(a, lat->nblocks, lat->stream); break;
+        default: launch_obs<M, ODD, StF16>(a, lat->nblocks, lat->stream); break;
+    }
+}
+
+static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, float *H, double *en_part) {
+    const WsLayout &L = lat->L;
+    ObsArgs a{};
+    a.pop = lat->ws + L.pop;
+    a.eps = reinterpret_cast<const float *>(lat->ws + L.eps);
+    a.mu = reinterpret_cast<const float *>(lat->ws + L.mu);
+    a.sig = reinterpret_cast<const float *>(lat->ws + L.sig);
+    a.nx = lat->d.nx;
+    a.ny = lat->d.ny;
+    a.nz = lat->d.nz;
+    a.N = lat->N;
+    a.inv_scale = lat->inv_scale;
+    if (lat->nsrc > 0) {
+        a.src_blk = reinterpret_cast<const int32_t *>(lat->ws + L.src_blk);
+        a.src_cell = reinterpret_cast<const int32_t *>(lat->ws + L.src_cell);
+        a.src_J0 = reinterpret_cast<const float *>(lat->ws + L.src_J0);
+        a.src_w = float(std::sin(two_pi_frac(double(lat->t), lat->src_period, lat->src_phase)));
+    }
+    a.E = E;
+    a.B = B;
+    a.D = D;
+    a.H = H;
+    a.en_part = en_part;
+    const int odd = int(lat->t & 1);
+    if (lat->d.model == LBEM_MM) {
+        if (odd) dispatch_obs_storage<MM, 1>(lat, a);
+        else dispatch_obs_storage<MM, 0>(lat, a);
+    } else {
+        if (odd) dispatch_obs_storage<HV, 1>(lat, a);
+        else dispatch_obs_storage<HV, 0>(lat, a);
+    }
+    return hip_check(hipGetLastError(), "observe launch");
+}
+
+lbem_status lbem_get_fields(lbem_lattice *lat, float *E, float *B, float *D, float *H) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    return observe(lat, E, B, D, H, nullptr);
+}
+
+lbem_status lbem_energy(lbem_lattice *lat, double *out) {
+    if (!lat || !out) return fail(LBEM_EINVAL, "null argument");
+    double *part = reinterpret_cast<double *>(lat->ws + lat->L.en_part);
+    lbem_status st = observe(lat, nullptr, nullptr, nullptr, nullptr, part);
+    if (st) return st;
+    hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream, part, lat->nblocks, out);
+    return hip_check(hipGetLastError(), "energy sum");
+}
+
+lbem_status lbem_save_state(lbem_lattice *lat, void *dst) {
+    if (!lat || !dst) return fail(LBEM_EINVAL, "null argument");
+    const size_t bytes = size_t(lat->N) * lat->Q * lat->sbytes;
+    return hip_check(hipMemcpyAsync(dst, lat->ws + lat->L.pop, bytes, hipMemcpyDeviceToDevice, lat->stream), "save");
+}
+
+lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t) {
+    if (!lat || !src) return fail(LBEM_EINVAL, "null argument");
+    if (t < 0) return fail(LBEM_EINVAL, "time level < 0");
+    const size_t bytes = size_t(lat->N) * lat->Q * lat->sbytes;
+    lbem_status st =
+        hip_check(hipMemcpyAsync(lat->ws + lat->L.pop, src, bytes, hipMemcpyDeviceToDevice, lat->stream), "load");
+    if (st) return st;
+    lat->t = t;
+    return LBEM_OK;
+}

@@ -1,0 +1,329 @@
+// lbem_model.hpp -- lattice tables and the per-cell collision of the two
+// Maxwell lattice-Boltzmann schemes, as device code for gfx950.
+//
+// Population numbering (shared by every kernel of this library):
+//   MM: q = r * 24 + p * 8 + i * 2 + j for the moving populations f^{p(r)}_{ij}
+//       (r = 0 electric, 1 magnetic; plane p = 0..2; direction i = 0..3 for the
+//       paper's i = 1..4; j = 0, 1), q = 48 and 49 for the rest populations
+//       f_0^(0), f_0^(1).
+//   HV: q = r * 18 + i * 3 + a for component a of e_i (r = 0) or h_i (r = 1),
+//       i = 0..5 for the paper's i = 1..6.
+// The opposite of q (same r, j or component, reversed velocity) is the slot
+// that the in-place AA streaming of the step kernels swaps with.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbem {
+
+// ---------------------------------------------------------------- MM tables
+// eq. (VelocitySetMiller): v_i^p = sqrt(2) (cos, sin)((2i - 1) pi / 4) in the
+// plane p (xy, xz, yz).  The components are exactly 0 or +-1.
+constexpr int kMMV[3][4][3] = {
+    {{1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}},
+    {{1, 0, 1}, {-1, 0, 1}, {-1, 0, -1}, {1, 0, -1}},
+    {{0, 1, 1}, {0, -1, 1}, {0, -1, -1}, {0, 1, -1}},
+};
+// eq. (ElectromagneticVectorsMiller): e_{i0} = v_{[(i+2) mod 4]+1} / 2 in the
+// paper's 1-based i, i.e. 2 e_{i0} = v[(i + 3) mod 4] for 0-based i, and
+// e_{i1} = -e_{i0}.  b_{ij} = v_i x e_{ij} is the same for all i of a plane:
+// b_{i0} = kMMB[p], b_{i1} = -kMMB[p].
+constexpr int mm_e2(int p, int i, int a) { return kMMV[p][(i + 3) % 4][a]; }
+constexpr int kMMB[3][3] = {{0, 0, -1}, {0, 1, 0}, {-1, 0, 0}};
+
+constexpr int mm_cross_e_b(int p, int i, int a) {
+    // (v x e_{i0})_a * 2 computed from the tables, for the static checks below
+    return a == 0 ? kMMV[p][i][1] * mm_e2(p, i, 2) - kMMV[p][i][2] * mm_e2(p, i, 1)
+         : a == 1 ? kMMV[p][i][2] * mm_e2(p, i, 0) - kMMV[p][i][0] * mm_e2(p, i, 2)
+                  : kMMV[p][i][0] * mm_e2(p, i, 1) - kMMV[p][i][1] * mm_e2(p, i, 0);
+}
+constexpr bool mm_tables_consistent() {
+    for (int p = 0; p < 3; ++p)
+        for (int i = 0; i < 4; ++i) {
+            int dot = 0;
+            for (int a = 0; a < 3; ++a) {
+                if (kMMV[p][(i + 2) % 4][a] != -kMMV[p][i][a]) return false;  // opposite pairs
+                if (mm_cross_e_b(p, i, a) != 2 * kMMB[p][a]) return false;     // b = v x e
+                dot += kMMV[p][i][a] * mm_e2(p, i, a);
+            }
+            if (dot != 0) return false;  // e perpendicular to v
+        }
+    return true;
+}
+static_assert(mm_tables_consistent(), "MM vector tables");
+
+struct MM {
+    static constexpr int Q = 50;
+    static constexpr int kRestQ = 48;
+    __host__ __device__ static constexpr int vel(int q, int a) {
+        return q >= 48 ? 0 : kMMV[(q % 24) / 8][(q % 8) / 2][a];
+    }
+    __host__ __device__ static constexpr int opp(int q) {
+        return q >= 48 ? q : (q / 8) * 8 + ((((q % 8) / 2) + 2) % 4) * 2 + (q % 2);
+    }
+};
+
+// ---------------------------------------------------------------- HV tables
+// Section III velocity set: v1 = +x, v2 = +y, v3 = -x, v4 = -y, v5 = -z, v6 = +z.
+constexpr int kHVV[6][3] = {{1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}, {0, 0, 1}};
+constexpr int kHVOpp[6] = {2, 3, 0, 1, 5, 4};
+
+struct HV {
+    static constexpr int Q = 36;
+    __host__ __device__ static constexpr int vel(int q, int a) { return kHVV[(q % 18) / 3][a]; }
+    __host__ __device__ static constexpr int opp(int q) { return (q / 18) * 18 + kHVOpp[(q % 18) / 3] * 3 + q % 3; }
+};
+
+constexpr bool opp_consistent_mm() {
+    for (int q = 0; q < MM::Q; ++q) {
+        if (MM::opp(MM::opp(q)) != q) return false;
+        for (int a = 0; a < 3; ++a)
+            if (MM::vel(MM::opp(q), a) != -MM::vel(q, a)) return false;
+    }
+    return true;
+}
+constexpr bool opp_consistent_hv() {
+    for (int q = 0; q < HV::Q; ++q) {
+        if (HV::opp(HV::opp(q)) != q) return false;
+        for (int a = 0; a < 3; ++a)
+            if (HV::vel(HV::opp(q), a) != -HV::vel(q, a)) return false;
+    }
+    return true;
+}
+static_assert(opp_consistent_mm() && opp_consistent_hv(), "opposite-direction maps");
+
+// ---------------------------------------------------------------- per cell
+// x / d given inv = 1 / d (rounded): one Newton correction of the product makes
+// the quotient (nearly always) the correctly rounded one.  Multiplying by a
+// rounded reciprocal alone biases every update the same way, and over 10^4
+// steps that bias accumulates linearly into phase drift; rounding that is
+// unbiased only accumulates as a random walk.
+__device__ __forceinline__ float div_rn(float x, float d, float inv) {
+    const float q = x * inv;
+    const float r = __builtin_fmaf(-q, d, x);
+    return __builtin_fmaf(r, inv, q);
+}
+
+// Media and source seen by one cell at one step.
+struct CellMedia {
+    float eps_r, mu_r, sigma;
+};
+
+// Reported fields of one cell (pre-collision state).
+struct CellFields {
+    float E[3], B[3], D[3], H[3];
+};
+
+// MM collision (Section II): moments (eq. MacroscopicFieldsMiller), physical E
+// and current with both an ohmic and a prescribed part
+//   E = (D'/eps_r - mu0 Jsrc / (4 eps_r)) / (1 + mu0 sigma / (4 eps_r)),
+//   J = sigma E + Jsrc,                 (mu0 = 2)
+// equilibria (eq. equilibriumsMiller) and f' = 2 f_eq - f (eq. CollisionMiller,
+// applied to both rest populations).  f is overwritten with f'.
+__device__ __forceinline__ void mm_collide(float (&f)[50], const CellMedia &m, const float Js[3], CellFields &o) {
+    float D[3] = {0.f, 0.f, 0.f}, B[3] = {0.f, 0.f, 0.f};
+    float rho = f[48];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        float sb = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float d0 = f[p * 8 + i * 2] - f[p * 8 + i * 2 + 1];        // f_{i0} - f_{i1}, r = 0
+            const float d1 = f[24 + p * 8 + i * 2] - f[24 + p * 8 + i * 2 + 1];  // r = 1
+            rho += f[p * 8 + i * 2] + f[p * 8 + i * 2 + 1];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (mm_e2(p, i, a) != 0) D[a] += (mm_e2(p, i, a) > 0 ? 0.5f : -0.5f) * d0;
+            sb += d1;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (kMMB[p][a] != 0) B[a] += kMMB[p][a] > 0 ? sb : -sb;
+    }
+    // mu0 / 4 = 1/2:  E = (D' - Jsrc / 2) / (eps_r + sigma / 2)
+    const float den = m.eps_r + 0.5f * m.sigma;
+    const float inv = 1.0f / den;
+    float E[3], J[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        E[a] = div_rn(D[a] - 0.5f * Js[a], den, inv);
+        J[a] = m.sigma * E[a] + Js[a];
+        o.E[a] = E[a];
+        o.B[a] = B[a];
+        o.D[a] = m.eps_r * E[a];
+        o.H[a] = 0.5f * (B[a] / m.mu_r);
+    }
+    const float ke0 = 0.25f * m.eps_r, imu = 1.0f / m.mu_r;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        float bb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (kMMB[p][a] != 0) bb += kMMB[p][a] > 0 ? B[a] : -B[a];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float vj = 0.f, ee = 0.f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (kMMV[p][i][a] != 0) vj += kMMV[p][i][a] > 0 ? J[a] : -J[a];
+                if (mm_e2(p, i, a) != 0) ee += mm_e2(p, i, a) > 0 ? E[a] : -E[a];
+            }
+            ee *= 0.5f;                     // E . e_{i0}
+            const float a0 = vj * 0.0625f;  // v . J / 16
+            const float u0 = ke0 * ee + 0.125f * div_rn(bb, m.mu_r, imu);
+            const float u1 = 0.25f * ee + 0.125f * bb;
+            const int q0 = p * 8 + i * 2, q1 = 24 + p * 8 + i * 2;
+            f[q0] = 2.f * (a0 + u0) - f[q0];
+            f[q0 + 1] = 2.f * (a0 - u0) - f[q0 + 1];
+            f[q1] = 2.f * (a0 + u1) - f[q1];
+            f[q1 + 1] = 2.f * (a0 - u1) - f[q1 + 1];
+        }
+    }
+    f[48] = 2.f * rho - f[48];
+    f[49] = 2.f * rho - f[49];
+}
+
+// MM equilibrium of given E, B with J = 0 and rho_c = 0 (initialisation and
+// hard sources).
+__device__ __forceinline__ void mm_field_equilibrium(float (&f)[50], const CellMedia &m, const float E[3],
+                                                     const float B[3]) {
+    const float ke0 = 0.25f * m.eps_r, imu = 1.0f / m.mu_r;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        float bb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (kMMB[p][a] != 0) bb += kMMB[p][a] > 0 ? B[a] : -B[a];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float ee = 0.f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (mm_e2(p, i, a) != 0) ee += mm_e2(p, i, a) > 0 ? E[a] : -E[a];
+            ee *= 0.5f;
+            const float u0 = ke0 * ee + 0.125f * div_rn(bb, m.mu_r, imu);
+            const float u1 = 0.25f * ee + 0.125f * bb;
+            const int q0 = p * 8 + i * 2, q1 = 24 + p * 8 + i * 2;
+            f[q0] = u0;
+            f[q0 + 1] = -u0;
+            f[q1] = u1;
+            f[q1 + 1] = -u1;
+        }
+    }
+    f[48] = 0.f;
+    f[49] = 0.f;
+}
+
+// HV lattice constants: eps0 = mu0 = 3 (vacuum speed 1/3, impedance 1).
+constexpr float kHVEps0 = 3.0f, kHVMu0 = 3.0f;
+
+// cross product of an axis velocity with a vector, component a
+template <int I>
+__device__ __forceinline__ float hv_vcross(const float w[3], int a) {
+    constexpr int vx = kHVV[I][0], vy = kHVV[I][1], vz = kHVV[I][2];
+    return a == 0 ? vy * w[2] - vz * w[1] : a == 1 ? vz * w[0] - vx * w[2] : vx * w[1] - vy * w[0];
+}
+
+template <int I>
+__device__ __forceinline__ void hv_collide_dir(float (&f)[36], const float D[3], const float B[3], const float E[3],
+                                               const float H[3], const float J[3]) {
+    constexpr int vx = kHVV[I][0], vy = kHVV[I][1], vz = kHVV[I][2];
+    const float Jv = vx * J[0] + vy * J[1] + vz * J[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int va = a == 0 ? vx : a == 1 ? vy : vz;
+        const int qe = I * 3 + a, qh = 18 + I * 3 + a;
+        // e' = 2 e_eq - e + T,  e_eq = (D - 3 v x H) / 6,  T = -(J.v) v / 2
+        const float ee = div_rn(D[a] - 3.f * hv_vcross<I>(H, a), 6.f, 1.f / 6.f);
+        f[qe] = 2.f * ee - f[qe] - 0.5f * Jv * va;
+        // h' = 2 h_eq - h,  h_eq = (B + 3 v x E) / 6
+        const float he = div_rn(B[a] + 3.f * hv_vcross<I>(E, a), 6.f, 1.f / 6.f);
+        f[qh] = 2.f * he - f[qh];
+    }
+}
+
+// Modified HV collision (Section III): D = sum e_i, B = sum h_i (eq.
+// MacroscopicFieldsHV), E = D / eps, H = B / mu, J = sigma E + Jsrc, equilibria
+// of eq. (equilibriumHV), e' = 2 e_eq - e + T (eq. CollisionmodifiedHV),
+// h' = 2 h_eq - h.
+__device__ __forceinline__ void hv_collide(float (&f)[36], const CellMedia &m, const float Js[3], CellFields &o) {
+    float D[3], B[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        D[a] = ((f[a] + f[3 + a]) + (f[6 + a] + f[9 + a])) + (f[12 + a] + f[15 + a]);
+        B[a] = ((f[18 + a] + f[21 + a]) + (f[24 + a] + f[27 + a])) + (f[30 + a] + f[33 + a]);
+    }
+    const float eps = kHVEps0 * m.eps_r, mu = kHVMu0 * m.mu_r;
+    const float ie = 1.0f / eps, im = 1.0f / mu;
+    float E[3], H[3], J[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        E[a] = div_rn(D[a], eps, ie);
+        H[a] = div_rn(B[a], mu, im);
+        J[a] = m.sigma * E[a] + Js[a];
+        o.E[a] = E[a];
+        o.B[a] = B[a];
+        o.D[a] = D[a];
+        o.H[a] = H[a];
+    }
+    hv_collide_dir<0>(f, D, B, E, H, J);
+    hv_collide_dir<1>(f, D, B, E, H, J);
+    hv_collide_dir<2>(f, D, B, E, H, J);
+    hv_collide_dir<3>(f, D, B, E, H, J);
+    hv_collide_dir<4>(f, D, B, E, H, J);
+    hv_collide_dir<5>(f, D, B, E, H, J);
+}
+
+template <int I>
+__device__ __forceinline__ void hv_eq_dir(float (&f)[36], const float D[3], const float B[3], const float E[3],
+                                          const float H[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f[I * 3 + a] = div_rn(D[a] - 3.f * hv_vcross<I>(H, a), 6.f, 1.f / 6.f);
+        f[18 + I * 3 + a] = div_rn(B[a] + 3.f * hv_vcross<I>(E, a), 6.f, 1.f / 6.f);
+    }
+}
+
+// HV equilibrium of given E, B (D = eps E, H = B / mu).
+__device__ __forceinline__ void hv_field_equilibrium(float (&f)[36], const CellMedia &m, const float E[3],
+                                                     const float B[3]) {
+    const float eps = kHVEps0 * m.eps_r, mu = kHVMu0 * m.mu_r;
+    const float im = 1.0f / mu;
+    float D[3], H[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        D[a] = eps * E[a];
+        H[a] = div_rn(B[a], mu, im);
+    }
+    hv_eq_dir<0>(f, D, B, E, H);
+    hv_eq_dir<1>(f, D, B, E, H);
+    hv_eq_dir<2>(f, D, B, E, H);
+    hv_eq_dir<3>(f, D, B, E, H);
+    hv_eq_dir<4>(f, D, B, E, H);
+    hv_eq_dir<5>(f, D, B, E, H);
+}
+
+// model dispatch
+template <class M>
+struct Cell;
+template <>
+struct Cell<MM> {
+    __device__ static void collide(float (&f)[50], const CellMedia &m, const float Js[3], CellFields &o) {
+        mm_collide(f, m, Js, o);
+    }
+    __device__ static void equilibrium(float (&f)[50], const CellMedia &m, const float E[3], const float B[3]) {
+        mm_field_equilibrium(f, m, E, B);
+    }
+};
+template <>
+struct Cell<HV> {
+    __device__ static void collide(float (&f)[36], const CellMedia &m, const float Js[3], CellFields &o) {
+        hv_collide(f, m, Js, o);
+    }
+    __device__ static void equilibrium(float (&f)[36], const CellMedia &m, const float E[3], const float B[3]) {
+        hv_field_equilibrium(f, m, E, B);
+    }
+};
+
+}  // namespace lbem

@@ -1,0 +1,257 @@
+"""Thin ctypes binding of ``liblbem.so`` (include/lbem.h).
+
+Only argument marshalling happens here: torch provides device memory and the
+stream, every step of the computation runs in the library's HIP kernels.  If
+the library is not built, or no GPU is present, constructing a lattice raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbem.so")
+
+MODEL = {"mm": 0, "hv": 1}
+STORAGE = {"f32": 0, "bf16": 1, "f16": 2}
+NQ = {"mm": 50, "hv": 36}
+STATUS = {0: "LBEM_OK", -1: "LBEM_EINVAL", -2: "LBEM_ENOMEM", -3: "LBEM_EHIP", -4: "LBEM_EUNSTABLE",
+          -5: "LBEM_ESTATE", -6: "LBEM_ENOTFINITE"}
+
+# every function include/lbem.h declares, with its ctypes signature
+_P, _I32, _I64, _D, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+SIGNATURES = {
+    "lbem_version": (_I32, []),
+    "lbem_last_error": (C.c_char_p, []),
+    "lbem_workspace_size": (_I32, [_P, C.POINTER(_SZ)]),
+    "lbem_state_size": (_I32, [_P, C.POINTER(_SZ)]),
+    "lbem_create": (_I32, [_P, _P, _P, _P, _P, _SZ, _P, C.POINTER(_P)]),
+    "lbem_destroy": (_I32, [_P]),
+    "lbem_set_stream": (_I32, [_P, _P]),
+    "lbem_set_fields": (_I32, [_P, _P, _P]),
+    "lbem_set_current_source": (_I32, [_P, _I32, _P, _P, _D, _D]),
+    "lbem_set_plane_source": (_I32, [_P, _I32, _P, _P, _D]),
+    "lbem_set_probes": (_I32, [_P, _I32, _P, _I64, _P]),
+    "lbem_set_detector": (_I32, [_P, _I32]),
+    "lbem_detector_read": (_I32, [_P, _P]),
+    "lbem_set_energy_series": (_I32, [_P, _I32, _I64, _P]),
+    "lbem_step": (_I32, [_P, _I64]),
+    "lbem_get_time": (_I32, [_P, C.POINTER(_I64)]),
+    "lbem_get_fields": (_I32, [_P, _P, _P, _P, _P]),
+    "lbem_energy": (_I32, [_P, _P]),
+    "lbem_save_state": (_I32, [_P, _P]),
+    "lbem_load_state": (_I32, [_P, _P, _I64]),
+}
+
+
+class LbemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Desc(C.Structure):
+    _fields_ = [("model", C.c_int32), ("storage", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nz", C.c_int32), ("reserved", C.c_int32), ("storage_scale", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblbem.so and declare its signatures (no GPU needed to load)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+        lib = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status: int):
+    if status != 0:
+        raise LbemError(status, load_library().lbem_last_error().decode())
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev_f32(a, n: int, device) -> Optional[torch.Tensor]:
+    if a is None:
+        return None
+    t = torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a)
+    t = t.to(device=device, dtype=torch.float32).contiguous().reshape(-1)
+    if t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def desc(model: str, shape, storage: str = "f32", storage_scale: float = 0.0) -> Desc:
+    nx, ny, nz = shape
+    return Desc(MODEL[model], STORAGE[storage], nx, ny, nz, 0, float(storage_scale))
+
+
+def workspace_size(model: str, shape, storage: str = "f32") -> int:
+    lib = load_library()
+    out = C.c_size_t()
+    d = desc(model, shape, storage)
+    check(lib.lbem_workspace_size(C.byref(d), C.byref(out)))
+    return out.value
+
+
+class Lattice:
+    """One periodic nx*ny*nz lattice of the MM or HV model on the current GPU."""
+
+    def __init__(self, model: str, shape, eps_r=None, mu_r=None, sigma=None, storage: str = "f32",
+                 storage_scale: float = 0.0, device="cuda", stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the lbem library needs a GPU; none is visible")
+        self.lib = load_library()
+        self.model, self.shape, self.storage = model, tuple(int(s) for s in shape), storage
+        nx, ny, nz = self.shape
+        self.n = nx * ny * nz
+        self.device = torch.device(device)
+        self._desc = desc(model, self.shape, storage, storage_scale)
+        size = C.c_size_t()
+        check(self.lib.lbem_workspace_size(C.byref(self._desc), C.byref(size)))
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        media = [_dev_f32(x, self.n, self.device) for x in (eps_r, mu_r, sigma)]
+        h = C.c_void_p()
+        self._stream = stream
+        check(self.lib.lbem_create(C.byref(self._desc), *[_ptr(m) for m in media], _ptr(self.workspace),
+                                   size.value, C.c_void_p(_stream_ptr(stream)), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ set-up
+    def set_fields(self, E, B):
+        E = _dev_f32(E, 3 * self.n, self.device)
+        B = _dev_f32(B, 3 * self.n, self.device)
+        check(self.lib.lbem_set_fields(self.h, _ptr(E), _ptr(B)))
+        self._keep["fields0"] = (E, B)  # kept alive until the stream has consumed them
+
+    def set_current_source(self, cells: Sequence[int], J0, period: float, phase: float = 0.0):
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+        J0 = np.ascontiguousarray(np.asarray(J0, dtype=np.float32).reshape(-1, 3))
+        check(self.lib.lbem_set_current_source(self.h, len(cells), cells.ctypes.data_as(C.c_void_p),
+                                               J0.ctypes.data_as(C.c_void_p), float(period), float(phase)))
+
+    def set_currents(self, currents):
+        """Point currents as (cell, J0[3], period, phase) sharing one period and phase."""
+        if not currents:
+            check(self.lib.lbem_set_current_source(self.h, 0, None, None, 1.0, 0.0))
+            return
+        periods = {c[2] for c in currents}
+        phases = {c[3] for c in currents}
+        if len(periods) != 1 or len(phases) != 1:
+            raise ValueError("all currents of a lattice share one period and phase")
+        self.set_current_source([c[0] for c in currents], [c[1] for c in currents], periods.pop(), phases.pop())
+
+    def set_plane_source(self, z: int, E0, B0, period: float):
+        E0 = np.ascontiguousarray(np.asarray(E0, dtype=np.float32))
+        B0 = np.ascontiguousarray(np.asarray(B0, dtype=np.float32))
+        check(self.lib.lbem_set_plane_source(self.h, int(z), E0.ctypes.data_as(C.c_void_p),
+                                             B0.ctypes.data_as(C.c_void_p), float(period)))
+
+    def set_probes(self, cells: Sequence[int], cap_rows: int) -> torch.Tensor:
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+        series = torch.zeros((cap_rows, len(cells), 6), dtype=torch.float64, device=self.device)
+        check(self.lib.lbem_set_probes(self.h, len(cells), cells.ctypes.data_as(C.c_void_p), int(cap_rows),
+                                       _ptr(series)))
+        self._keep["probes"] = series
+        return series
+
+    def set_detector(self, z: int):
+        check(self.lib.lbem_set_detector(self.h, int(z)))
+
+    def detector(self) -> torch.Tensor:
+        out = torch.zeros(1, dtype=torch.float64, device=self.device)
+        check(self.lib.lbem_detector_read(self.h, _ptr(out)))
+        return out
+
+    def set_energy_series(self, every: int, cap: int) -> torch.Tensor:
+        series = torch.zeros(cap, dtype=torch.float64, device=self.device)
+        check(self.lib.lbem_set_energy_series(self.h, int(every), int(cap), _ptr(series)))
+        self._keep["energy"] = series
+        return series
+
+    def set_stream(self, stream: Optional[torch.cuda.Stream]):
+        self._stream = stream
+        check(self.lib.lbem_set_stream(self.h, C.c_void_p(_stream_ptr(stream))))
+
+    # ------------------------------------------------------------ run
+    def step(self, nsteps: int = 1):
+        check(self.lib.lbem_step(self.h, int(nsteps)))
+
+    @property
+    def time(self) -> int:
+        t = C.c_int64()
+        check(self.lib.lbem_get_time(self.h, C.byref(t)))
+        return t.value
+
+    def fields(self):
+        """(E, B, D, H), each a [3][N] float32 device tensor."""
+        outs = [torch.empty((3, self.n), dtype=torch.float32, device=self.device) for _ in range(4)]
+        check(self.lib.lbem_get_fields(self.h, *[_ptr(o) for o in outs]))
+        return tuple(outs)
+
+    def energy(self) -> torch.Tensor:
+        out = torch.zeros(1, dtype=torch.float64, device=self.device)
+        check(self.lib.lbem_energy(self.h, _ptr(out)))
+        return out
+
+    def state_size(self) -> int:
+        out = C.c_size_t()
+        check(self.lib.lbem_state_size(C.byref(self._desc), C.byref(out)))
+        return out.value
+
+    def save_state(self, dst: Optional[torch.Tensor] = None):
+        if dst is None:
+            dst = torch.empty(self.state_size(), dtype=torch.uint8, device=self.device)
+        check(self.lib.lbem_save_state(self.h, _ptr(dst)))
+        return dst, self.time
+
+    def load_state(self, src: torch.Tensor, t: int):
+        if src.numel() * src.element_size() < self.state_size():
+            raise ValueError("state buffer too small")
+        check(self.lib.lbem_load_state(self.h, _ptr(src), int(t)))
+
+
+def lattice_from_workload(w, storage: str = "f32", storage_scale: float = 0.0) -> Lattice:
+    """Set up a Lattice from an inputs.Workload (media, fields, sources, probes, detector)."""
+    lat = Lattice(w.model, w.shape, w.eps_r, w.mu_r, w.sigma, storage=storage, storage_scale=storage_scale)
+    lat.set_fields(*w.fields0())
+    if w.currents:
+        lat.set_currents(w.currents)
+    if w.plane is not None:
+        z, E0, B0, period = w.plane
+        lat.set_plane_source(z, E0, B0, period)
+    if w.det_z is not None:
+        lat.set_detector(w.det_z)
+    return lat

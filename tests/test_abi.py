@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports every
+function include/lbem.h declares, and rejects bad arguments before touching
+the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2309_08068_amd import lbem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(lbem_\w+)\s*\(", text))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbem.LIB_PATH):
+        from paper_2309_08068_amd import build
+        build.build()
+    return lbem.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares a signature for each of them
+    assert names <= set(lbem.SIGNATURES)
+
+
+def test_version(lib):
+    assert lib.lbem_version() >= 10000
+
+
+def ws(model="mm", shape=(4, 4, 4), storage="f32", scale=0.0, reserved=0):
+    d = lbem.desc(model, shape, storage, scale)
+    d.reserved = reserved
+    out = C.c_size_t()
+    st = lbem.load_library().lbem_workspace_size(C.byref(d), C.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_grows_with_model_and_storage(lib):
+    st1, b_mm = ws("mm", (16, 16, 16))
+    st2, b_hv = ws("hv", (16, 16, 16))
+    st3, b_bf = ws("mm", (16, 16, 16), "bf16")
+    assert st1 == st2 == st3 == 0
+    n = 16 ** 3
+    assert b_mm >= n * 50 * 4 + 12 * n
+    assert b_hv >= n * 36 * 4 + 12 * n
+    assert b_bf >= n * 50 * 2 + 12 * n and b_bf < b_mm
+    out = C.c_size_t()
+    d = lbem.desc("mm", (16, 16, 16), "bf16")
+    assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0 and out.value == n * 50 * 2
+
+
+@pytest.mark.parametrize("kw", [dict(shape=(0, 4, 4)), dict(shape=(4, -1, 4)), dict(reserved=1),
+                                dict(storage="f16", scale=3.0), dict(storage="f16", scale=-2.0),
+                                dict(shape=(2048, 1024, 1024))])
+def test_bad_descriptors_rejected(lib, kw):
+    st, _ = ws(**kw)
+    assert st == -1
+    assert lib.lbem_last_error()
+
+
+def test_bad_model_and_storage_rejected(lib):
+    d = lbem.desc("mm", (4, 4, 4))
+    d.model = 7
+    out = C.c_size_t()
+    assert lib.lbem_workspace_size(C.byref(d), C.byref(out)) == -1
+    d = lbem.desc("mm", (4, 4, 4))
+    d.storage = 9
+    assert lib.lbem_workspace_size(C.byref(d), C.byref(out)) == -1
+    assert lib.lbem_workspace_size(None, C.byref(out)) == -1
+
+
+def test_create_validates_host_arguments_first(lib):
+    d = lbem.desc("mm", (4, 4, 4))
+    h = C.c_void_p()
+    # null workspace, misaligned workspace, too-small workspace, null out: no device work happens
+    assert lib.lbem_create(C.byref(d), None, None, None, None, 0, None, C.byref(h)) == -1
+    assert lib.lbem_create(C.byref(d), None, None, None, C.c_void_p(0x1001), 1 << 30, None, C.byref(h)) == -1
+    assert lib.lbem_create(C.byref(d), None, None, None, C.c_void_p(0x100000), 16, None, C.byref(h)) == -2
+    assert lib.lbem_create(C.byref(d), None, None, None, C.c_void_p(0x100000), 1 << 30, None, None) == -1
+
+
+def test_null_handles_rejected(lib):
+    assert lib.lbem_step(None, 1) == -1
+    assert lib.lbem_destroy(None) == -1
+    assert lib.lbem_get_fields(None, None, None, None, None) == -1
+    assert lib.lbem_energy(None, None) == -1
