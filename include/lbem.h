@@ -163,6 +163,98 @@ lbem_status lbem_energy(lbem_lattice *lat, double *out);
 lbem_status lbem_save_state(lbem_lattice *lat, void *dst);
 lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t);
 
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse-time) differentiation of the detector loss.
+ *
+ * The step is affine in the populations for fixed media, f_{n+1} = S C_theta f_n
+ * (S the advection, C_theta the per-cell collision of Sections II-III), so the
+ * loss L = sum_{n=t0}^{t0+N-1} sum_{plane z_d} |E(f_n)|^2 has the adjoint
+ *   lambda_n = C_theta^T S^T lambda_{n+1} + dl_n/df_n,   lambda_{t0+N} = 0,
+ * and dL/dtheta_x accumulates mu_n(x)^T (dC_theta/dtheta_x) f_n(x) + dl_n/dtheta_x
+ * with mu_n = S^T lambda_{n+1}; the first term needs only E(f_n) at x because
+ * C(f) = 2 f_eq(m(f); theta) - f.  theta = (eps_r, sigma) per cell, mu_r fixed.
+ * Memory: the forward stores a checkpoint every K steps; the backward
+ * recomputes each segment storing E(f_n) per step (FP32 frames), then runs
+ * the segment's adjoint steps in reverse (in-place AA streaming with reversed
+ * velocities).  Gradients accumulate in FP64.  Model MM only (HV has a
+ * growing interface mode, which makes its gradients meaningless over long
+ * runs); no soft or hard sources may be set.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of adjoint workspace for nsteps steps with a checkpoint every K. */
+lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, int32_t K, size_t *bytes);
+
+/* Run nsteps steps from the current state (time level t0) recording
+ * checkpoints in ws, and write L (sum over the collided states of the plane
+ * det_z of |E|^2, FP64) to loss (dev double [1]).  Leaves the lattice at
+ * t0 + nsteps.  LBEM_ESTATE if sources are set or the model is not MM. */
+lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t det_z, void *ws,
+                                 size_t ws_bytes, double *loss);
+
+/* Reverse pass for the last lbem_adjoint_forward with this ws: writes
+ * dL/deps_r and dL/dsigma (dev double [N]) times `scale`.  If E0 and B0 (dev
+ * float [3][N]) are given, the state at t0 is taken to be f_eq(E0, B0) of the
+ * current media (lbem_set_fields), and its dependence on eps_r is included.
+ * Leaves the lattice state as the forward left it. */
+lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, const float *E0, const float *B0,
+                                  double scale, double *grad_eps, double *grad_sigma);
+
+/* ------------------------------------------------------------------------
+ * Batched ragged 1-D lattices (Section IV-D generalised to many stacks).
+ *
+ * n independent periodic 1 x 1 x L_b lattices of one model, concatenated:
+ * instance b owns cells [offsets[b], offsets[b+1]) of every per-cell array.
+ * All instances share the time level.  One call of lbem_batch_step advances
+ * every instance by nsteps steps in ONE persistent kernel launch: each
+ * workgroup owns whole instances (longest first, to the least-loaded
+ * workgroup) and separates the steps of an instance by a workgroup barrier,
+ * so no grid-wide synchronisation is needed.  In 1-D only the z components of
+ * the velocities stream; MM's xy-plane populations and HV's +-x, +-y
+ * populations stay in their cell.
+ * ------------------------------------------------------------------------ */
+typedef struct lbem_batch lbem_batch;
+
+/* offsets: host int64 [n + 1], offsets[0] = 0, strictly increasing, total < 2^31. */
+lbem_status lbem_batch_workspace_size(int32_t model, int32_t storage, int32_t n, const int64_t *offsets,
+                                      size_t *bytes);
+
+/* eps_r, mu_r, sigma: dev float [total] or NULL (1, 1, 0); validated as in
+ * lbem_create (synchronises the stream once).  storage as lbem_storage
+ * (FP16 uses no scale). */
+lbem_status lbem_batch_create(int32_t model, int32_t storage, int32_t n, const int64_t *offsets, const float *eps_r,
+                              const float *mu_r, const float *sigma, void *workspace, size_t workspace_bytes,
+                              void *stream, lbem_batch **out);
+lbem_status lbem_batch_destroy(lbem_batch *b);
+
+/* f := f_eq(E, B, J = 0) in every cell; E, B dev float [3][total].  Time level 0. */
+lbem_status lbem_batch_set_fields(lbem_batch *b, const float *E, const float *B);
+
+/* Launch shape of the persistent kernel: threads per workgroup (64, 128, 256,
+ * 512 or 1024) and workgroups per compute unit (>= 1).  Re-plans the
+ * instance assignment. */
+lbem_status lbem_batch_set_launch(lbem_batch *b, int32_t threads, int32_t groups_per_cu);
+
+/* Time each candidate launch shape over trial_steps steps (the state is saved
+ * and restored, so the batch is left unchanged) and keep the fastest.
+ * Synchronises the stream.  The chosen shape is written to threads / groups_per_cu
+ * (either may be NULL). */
+lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *threads, int32_t *groups_per_cu);
+
+/* Advance every instance by nsteps steps: one persistent kernel launch. */
+lbem_status lbem_batch_step(lbem_batch *b, int64_t nsteps);
+
+/* The same nsteps as a HIP graph holding the persistent launch, captured on
+ * first use for this (nsteps, parity) and replayed afterwards. */
+lbem_status lbem_batch_step_graph(lbem_batch *b, int64_t nsteps);
+
+/* Reference schedule: one kernel launch per instance per step. */
+lbem_status lbem_batch_step_per_instance(lbem_batch *b, int64_t nsteps);
+
+/* Reported fields (as lbem_get_fields) of every cell: dev float [3][total] or NULL. */
+lbem_status lbem_batch_get_fields(lbem_batch *b, float *E, float *B);
+
+lbem_status lbem_batch_get_time(lbem_batch *b, int64_t *t);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,555 @@
+// lbem_batch.hip -- many independent ragged 1-D lattices advanced by one
+// persistent kernel launch (the batched form of the stepper; include/lbem.h).
+//
+// Every workgroup owns a list of whole instances, planned on the host longest
+// first onto the least-loaded workgroup.  It advances each of its instances
+// through all requested steps, one barrier per step; instances never share
+// cells, so no grid-wide synchronisation exists.  The per-cell update is the
+// same collision and in-place AA streaming as the 3-D kernels, restricted to
+// the z component of the velocities (x and y wrap onto the cell itself).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <queue>
+#include <vector>
+
+#include "../../include/lbem.h"
+#include "lbem_common.hpp"
+#include "lbem_internal.hpp"
+#include "lbem_util_kernels.hpp"
+
+using namespace lbem;
+
+namespace {
+
+constexpr int kMaxGroups = 4096;
+
+struct BatchArgs {
+    void *pop;
+    const float *eps, *mu, *sig;
+    const int32_t *inst_off;  // [n + 1]
+    const int32_t *wg_start;  // [G + 1] ranges into items
+    const int32_t *items;     // instance ids
+    size_t total;
+    int64_t nsteps;
+    int32_t parity;  // time level parity at the first step
+};
+
+// One cell of a 1-D instance occupying global cells [s, s + L).
+template <class M, int ODD, class ST>
+__device__ __forceinline__ void cell_1d(typename ST::T *__restrict__ pop, size_t total, const float *eps,
+                                        const float *mu, const float *sig, uint32_t s, uint32_t L, uint32_t i,
+                                        CellFields *out) {
+    const uint32_t g = s + i;
+    const uint32_t gm = s + (i == 0 ? L - 1 : i - 1);
+    const uint32_t gp = s + (i + 1 == L ? 0 : i + 1);
+    float f[M::Q];
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) {
+        const int vz = M::vel(q, 2);
+        if (ODD) f[q] = ST::load(pop + size_t(M::opp(q)) * total, vz > 0 ? gm : (vz < 0 ? gp : g), 1.f);
+        else f[q] = ST::load(pop + size_t(q) * total, g, 1.f);
+    }
+    const CellMedia m{eps[g], mu[g], sig[g]};
+    const float Js[3] = {0.f, 0.f, 0.f};
+    CellFields o;
+    Cell<M>::collide(f, m, Js, o);
+    if (out) {
+        *out = o;
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) {
+        const int vz = M::vel(q, 2);
+        if (ODD) ST::store(pop + size_t(q) * total, vz > 0 ? gp : (vz < 0 ? gm : g), f[q], 1.f);
+        else ST::store(pop + size_t(M::opp(q)) * total, g, f[q], 1.f);
+    }
+}
+
+template <class M, class ST, int T>
+__global__ __launch_bounds__(T) void batch_persistent(BatchArgs a) {
+    auto *pop = static_cast<typename ST::T *>(a.pop);
+    const int i0 = a.wg_start[blockIdx.x], i1 = a.wg_start[blockIdx.x + 1];
+    for (int it = i0; it < i1; ++it) {
+        const int b = a.items[it];
+        const uint32_t s = uint32_t(a.inst_off[b]);
+        const uint32_t L = uint32_t(a.inst_off[b + 1]) - s;
+        for (int64_t k = 0; k < a.nsteps; ++k) {
+            if (((a.parity + k) & 1) == 0) {
+                for (uint32_t i = threadIdx.x; i < L; i += T)
+                    cell_1d<M, 0, ST>(pop, a.total, a.eps, a.mu, a.sig, s, L, i, nullptr);
+            } else {
+                for (uint32_t i = threadIdx.x; i < L; i += T)
+                    cell_1d<M, 1, ST>(pop, a.total, a.eps, a.mu, a.sig, s, L, i, nullptr);
+            }
+            __syncthreads();  // the next step reads what neighbouring threads wrote
+        }
+    }
+}
+
+// One step of one instance (the per-instance reference schedule).
+template <class M, int ODD, class ST>
+__global__ __launch_bounds__(kBlock) void batch_one(BatchArgs a, uint32_t s, uint32_t L) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < L) cell_1d<M, ODD, ST>(static_cast<typename ST::T *>(a.pop), a.total, a.eps, a.mu, a.sig, s, L, i, nullptr);
+}
+
+template <class M, int ODD, class ST>
+__global__ __launch_bounds__(kBlock) void batch_fields(BatchArgs a, const int32_t *cell_inst, float *E, float *B) {
+    const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.total) return;
+    const int b = cell_inst[g];
+    const uint32_t s = uint32_t(a.inst_off[b]);
+    const uint32_t L = uint32_t(a.inst_off[b + 1]) - s;
+    CellFields o;
+    cell_1d<M, ODD, ST>(static_cast<typename ST::T *>(a.pop), a.total, a.eps, a.mu, a.sig, s, L, g - s, &o);
+    for (int d = 0; d < 3; ++d) {
+        if (E) E[d * a.total + g] = o.E[d];
+        if (B) B[d * a.total + g] = o.B[d];
+    }
+}
+
+template <class M, class ST>
+__global__ __launch_bounds__(kBlock) void batch_init(void *pop, const float *eps, const float *mu, const float *E,
+                                                     const float *B, uint32_t total) {
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= total) return;
+    const CellMedia m{eps[c], mu[c], 0.f};
+    const float e[3] = {E[c], E[size_t(total) + c], E[2 * size_t(total) + c]};
+    const float b[3] = {B[c], B[size_t(total) + c], B[2 * size_t(total) + c]};
+    float f[M::Q];
+    Cell<M>::equilibrium(f, m, e, b);
+    auto *p = static_cast<typename ST::T *>(pop);
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) ST::store(p + size_t(q) * total, c, f[q], 1.f);
+}
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BatchLayout {
+    size_t pop, backup, eps, mu, sig, inst_off, cell_inst, wg_start, items, flags, total;
+};
+
+BatchLayout batch_layout(int model, int storage, int32_t n, size_t total) {
+    BatchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = al(off + bytes);
+        return o;
+    };
+    const size_t pb = total * (model == LBEM_MM ? 50 : 36) * (storage == LBEM_F32 ? 4 : 2);
+    L.pop = take(pb);
+    L.backup = take(pb);
+    L.eps = take(total * 4);
+    L.mu = take(total * 4);
+    L.sig = take(total * 4);
+    L.inst_off = take((size_t(n) + 1) * 4);
+    L.cell_inst = take(total * 4);
+    L.wg_start = take((size_t(kMaxGroups) + 1) * 4);
+    L.items = take(size_t(n) * 4);
+    L.flags = take(64);
+    L.total = off;
+    return L;
+}
+
+lbem_status check_offsets(int32_t model, int32_t storage, int32_t n, const int64_t *offsets) {
+    if (model != LBEM_MM && model != LBEM_HV) return fail(LBEM_EINVAL, "unknown model %d", model);
+    if (storage < LBEM_F32 || storage > LBEM_F16) return fail(LBEM_EINVAL, "unknown storage %d", storage);
+    if (n < 1) return fail(LBEM_EINVAL, "need at least one instance");
+    if (!offsets) return fail(LBEM_EINVAL, "offsets is NULL");
+    if (offsets[0] != 0) return fail(LBEM_EINVAL, "offsets[0] must be 0");
+    for (int32_t b = 0; b < n; ++b)
+        if (offsets[b + 1] <= offsets[b]) return fail(LBEM_EINVAL, "instance %d is empty or offsets decrease", b);
+    if (offsets[n] >= (int64_t(1) << 31)) return fail(LBEM_EINVAL, "total cells must be < 2^31");
+    return LBEM_OK;
+}
+
+}  // namespace
+
+struct lbem_batch {
+    int model, storage;
+    int32_t n;
+    uint32_t total;
+    std::vector<int64_t> off;
+    hipStream_t stream;
+    char *ws;
+    BatchLayout L;
+    int ncu;
+    int threads, gpc, groups;
+    int64_t t;
+    // cached graph of one persistent launch
+    hipGraphExec_t gexec;
+    hipGraph_t graph;
+    int64_t g_nsteps;
+    int g_parity;
+    int g_threads, g_gpc;
+};
+
+namespace {
+
+template <class T>
+T *at(lbem_batch *b, size_t off) {
+    return reinterpret_cast<T *>(b->ws + off);
+}
+
+BatchArgs args_of(lbem_batch *b, int64_t nsteps) {
+    BatchArgs a{};
+    a.pop = b->ws + b->L.pop;
+    a.eps = at<const float>(b, b->L.eps);
+    a.mu = at<const float>(b, b->L.mu);
+    a.sig = at<const float>(b, b->L.sig);
+    a.inst_off = at<const int32_t>(b, b->L.inst_off);
+    a.wg_start = at<const int32_t>(b, b->L.wg_start);
+    a.items = at<const int32_t>(b, b->L.items);
+    a.total = b->total;
+    a.nsteps = nsteps;
+    a.parity = int32_t(b->t & 1);
+    return a;
+}
+
+// Longest-processing-time-first plan of instances onto `groups` workgroups.
+lbem_status plan(lbem_batch *b) {
+    const int G = b->groups;
+    std::vector<int32_t> order(b->n);
+    for (int32_t i = 0; i < b->n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        const int64_t lx = b->off[x + 1] - b->off[x], ly = b->off[y + 1] - b->off[y];
+        return lx != ly ? lx > ly : x < y;
+    });
+    using Bin = std::pair<int64_t, int>;  // (load, group)
+    std::priority_queue<Bin, std::vector<Bin>, std::greater<Bin>> heap;
+    for (int g = 0; g < G; ++g) heap.push({0, g});
+    std::vector<std::vector<int32_t>> bins(G);
+    for (int32_t i : order) {
+        Bin top = heap.top();
+        heap.pop();
+        bins[top.second].push_back(i);
+        top.first += b->off[i + 1] - b->off[i];
+        heap.push(top);
+    }
+    std::vector<int32_t> start(G + 1), items;
+    items.reserve(b->n);
+    for (int g = 0; g < G; ++g) {
+        start[g] = int32_t(items.size());
+        items.insert(items.end(), bins[g].begin(), bins[g].end());
+    }
+    start[G] = int32_t(items.size());
+    lbem_status st = hip_check(hipMemcpyAsync(b->ws + b->L.wg_start, start.data(), start.size() * 4,
+                                              hipMemcpyHostToDevice, b->stream), "copy plan");
+    if (!st) st = hip_check(hipMemcpyAsync(b->ws + b->L.items, items.data(), items.size() * 4, hipMemcpyHostToDevice,
+                                           b->stream), "copy plan");
+    if (!st) st = hip_check(hipStreamSynchronize(b->stream), "synchronise");
+    return st;
+}
+
+template <class M, class ST>
+void launch_persistent_t(lbem_batch *b, const BatchArgs &a, hipStream_t s) {
+    switch (b->threads) {
+        case 128: hipLaunchKernelGGL((batch_persistent<M, ST, 128>), dim3(b->groups), dim3(128), 0, s, a); break;
+        case 256: hipLaunchKernelGGL((batch_persistent<M, ST, 256>), dim3(b->groups), dim3(256), 0, s, a); break;
+        case 512: hipLaunchKernelGGL((batch_persistent<M, ST, 512>), dim3(b->groups), dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL((batch_persistent<M, ST, 1024>), dim3(b->groups), dim3(1024), 0, s, a); break;
+    }
+}
+
+template <class M>
+void launch_persistent_m(lbem_batch *b, const BatchArgs &a, hipStream_t s) {
+    switch (b->storage) {
+        case LBEM_F32: launch_persistent_t<M, StF32>(b, a, s); break;
+        case LBEM_BF16: launch_persistent_t<M, StBF16>(b, a, s); break;
+        default: launch_persistent_t<M, StF16>(b, a, s); break;
+    }
+}
+
+void launch_persistent(lbem_batch *b, int64_t nsteps, hipStream_t s) {
+    const BatchArgs a = args_of(b, nsteps);
+    if (b->model == LBEM_MM) launch_persistent_m<MM>(b, a, s);
+    else launch_persistent_m<HV>(b, a, s);
+}
+
+template <class M, int ODD, class ST>
+void launch_one(const BatchArgs &a, uint32_t s0, uint32_t L, hipStream_t s) {
+    hipLaunchKernelGGL((batch_one<M, ODD, ST>), dim3((L + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, s0, L);
+}
+
+template <class M, int ODD>
+void launch_one_st(lbem_batch *b, const BatchArgs &a, uint32_t s0, uint32_t L) {
+    switch (b->storage) {
+        case LBEM_F32: launch_one<M, ODD, StF32>(a, s0, L, b->stream); break;
+        case LBEM_BF16: launch_one<M, ODD, StBF16>(a, s0, L, b->stream); break;
+        default: launch_one<M, ODD, StF16>(a, s0, L, b->stream); break;
+    }
+}
+
+template <class M, int ODD, class ST>
+void launch_fields(lbem_batch *b, const BatchArgs &a, float *E, float *B) {
+    hipLaunchKernelGGL((batch_fields<M, ODD, ST>), dim3((b->total + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream,
+                       a, at<const int32_t>(b, b->L.cell_inst), E, B);
+}
+
+template <class M, int ODD>
+void launch_fields_st(lbem_batch *b, const BatchArgs &a, float *E, float *B) {
+    switch (b->storage) {
+        case LBEM_F32: launch_fields<M, ODD, StF32>(b, a, E, B); break;
+        case LBEM_BF16: launch_fields<M, ODD, StBF16>(b, a, E, B); break;
+        default: launch_fields<M, ODD, StF16>(b, a, E, B); break;
+    }
+}
+
+void drop_graph(lbem_batch *b) {
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace
+
+lbem_status lbem_batch_workspace_size(int32_t model, int32_t storage, int32_t n, const int64_t *offsets,
+                                      size_t *bytes) {
+    lbem_status st = check_offsets(model, storage, n, offsets);
+    if (st) return st;
+    if (!bytes) return fail(LBEM_EINVAL, "bytes is NULL");
+    *bytes = batch_layout(model, storage, n, size_t(offsets[n])).total;
+    return LBEM_OK;
+}
+
+lbem_status lbem_batch_create(int32_t model, int32_t storage, int32_t n, const int64_t *offsets, const float *eps_r,
+                              const float *mu_r, const float *sigma, void *workspace, size_t workspace_bytes,
+                              void *stream, lbem_batch **out) {
+    lbem_status st = check_offsets(model, storage, n, offsets);
+    if (st) return st;
+    if (!out || !workspace) return fail(LBEM_EINVAL, "null argument");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(LBEM_EINVAL, "workspace must be 256-byte aligned");
+    const size_t total = size_t(offsets[n]);
+    const BatchLayout L = batch_layout(model, storage, n, total);
+    if (workspace_bytes < L.total) return fail(LBEM_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    int dev = 0, ncu = 0;
+    st = hip_check(hipGetDevice(&dev), "get device");
+    if (!st) st = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+    if (st) return st;
+    auto *b = new (std::nothrow) lbem_batch();
+    if (!b) return fail(LBEM_ENOMEM, "host allocation failed");
+    b->model = model;
+    b->storage = storage;
+    b->n = n;
+    b->total = uint32_t(total);
+    b->off.assign(offsets, offsets + n + 1);
+    b->stream = static_cast<hipStream_t>(stream);
+    b->ws = static_cast<char *>(workspace);
+    b->L = L;
+    b->ncu = ncu > 0 ? ncu : 1;
+    b->threads = 256;
+    b->gpc = 2;
+    b->groups = std::min(kMaxGroups, b->ncu * b->gpc);
+    hipStream_t s = b->stream;
+    const uint32_t g = uint32_t((total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(fill_or_copy, dim3(g), dim3(kBlock), 0, s, at<float>(b, L.eps), eps_r, 1.0f, b->total);
+    hipLaunchKernelGGL(fill_or_copy, dim3(g), dim3(kBlock), 0, s, at<float>(b, L.mu), mu_r, 1.0f, b->total);
+    hipLaunchKernelGGL(fill_or_copy, dim3(g), dim3(kBlock), 0, s, at<float>(b, L.sig), sigma, 0.0f, b->total);
+    const size_t popw = (L.backup - L.pop) / 4;
+    hipLaunchKernelGGL(zero_bytes, dim3(uint32_t((popw + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       at<uint32_t>(b, L.pop), popw);
+    hipLaunchKernelGGL(zero_bytes, dim3(1), dim3(kBlock), 0, s, at<uint32_t>(b, L.flags), size_t(16));
+    std::vector<int32_t> off32(n + 1), cell_inst(total);
+    for (int32_t i = 0; i <= n; ++i) off32[i] = int32_t(offsets[i]);
+    for (int32_t i = 0; i < n; ++i)
+        std::fill(cell_inst.begin() + offsets[i], cell_inst.begin() + offsets[i + 1], i);
+    int32_t counts[4] = {0, 0, 0, 0};
+    hipLaunchKernelGGL(validate_media, dim3(g), dim3(kBlock), 0, s, at<const float>(b, L.eps), at<const float>(b, L.mu),
+                       at<const float>(b, L.sig), b->total, model, at<int32_t>(b, L.flags));
+    st = hip_check(hipGetLastError(), "launch");
+    if (!st) st = hip_check(hipMemcpyAsync(b->ws + L.inst_off, off32.data(), off32.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipMemcpyAsync(b->ws + L.cell_inst, cell_inst.data(), cell_inst.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipMemcpyAsync(counts, b->ws + L.flags, sizeof(counts), hipMemcpyDeviceToHost, s), "copy flags");
+    if (!st) st = hip_check(hipStreamSynchronize(s), "synchronise");
+    if (!st && counts[0]) st = fail(LBEM_ENOTFINITE, "%d cells have non-finite media", counts[0]);
+    if (!st && counts[1]) st = fail(LBEM_EINVAL, "%d cells have eps_r <= 0, mu_r <= 0 or sigma < 0", counts[1]);
+    if (!st && counts[2]) st = fail(LBEM_EUNSTABLE, "%d cells have eps_r * mu_r < 1", counts[2]);
+    if (!st && counts[3]) st = fail(LBEM_EUNSTABLE, "%d cells have sigma / (3 eps_r) >= 2 (HV current)", counts[3]);
+    if (!st) st = plan(b);
+    if (st) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return LBEM_OK;
+}
+
+lbem_status lbem_batch_destroy(lbem_batch *b) {
+    if (!b) return fail(LBEM_EINVAL, "batch is NULL");
+    drop_graph(b);
+    delete b;
+    return LBEM_OK;
+}
+
+template <class M>
+static void batch_init_m(lbem_batch *b, const float *E, const float *B) {
+    const uint32_t g = (b->total + kBlock - 1) / kBlock;
+    void *pop = b->ws + b->L.pop;
+    const float *eps = at<const float>(b, b->L.eps), *mu = at<const float>(b, b->L.mu);
+    switch (b->storage) {
+        case LBEM_F32: hipLaunchKernelGGL((batch_init<M, StF32>), dim3(g), dim3(kBlock), 0, b->stream, pop, eps, mu, E, B, b->total); break;
+        case LBEM_BF16: hipLaunchKernelGGL((batch_init<M, StBF16>), dim3(g), dim3(kBlock), 0, b->stream, pop, eps, mu, E, B, b->total); break;
+        default: hipLaunchKernelGGL((batch_init<M, StF16>), dim3(g), dim3(kBlock), 0, b->stream, pop, eps, mu, E, B, b->total); break;
+    }
+}
+
+lbem_status lbem_batch_set_fields(lbem_batch *b, const float *E, const float *B) {
+    if (!b || !E || !B) return fail(LBEM_EINVAL, "null argument");
+    if (b->model == LBEM_MM) batch_init_m<MM>(b, E, B);
+    else batch_init_m<HV>(b, E, B);
+    b->t = 0;
+    return hip_check(hipGetLastError(), "init launch");
+}
+
+lbem_status lbem_batch_set_launch(lbem_batch *b, int32_t threads, int32_t groups_per_cu) {
+    if (!b) return fail(LBEM_EINVAL, "batch is NULL");
+    if (threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(LBEM_EINVAL, "threads must be 128, 256, 512 or 1024");
+    if (groups_per_cu < 1 || int64_t(groups_per_cu) * b->ncu > kMaxGroups)
+        return fail(LBEM_EINVAL, "groups_per_cu must be in [1, %d]", kMaxGroups / b->ncu);
+    b->threads = threads;
+    b->gpc = groups_per_cu;
+    b->groups = b->ncu * groups_per_cu;
+    return plan(b);
+}
+
+lbem_status lbem_batch_step(lbem_batch *b, int64_t nsteps) {
+    if (!b) return fail(LBEM_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(LBEM_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return LBEM_OK;
+    launch_persistent(b, nsteps, b->stream);
+    lbem_status st = hip_check(hipGetLastError(), "persistent launch");
+    if (!st) b->t += nsteps;
+    return st;
+}
+
+lbem_status lbem_batch_step_graph(lbem_batch *b, int64_t nsteps) {
+    if (!b) return fail(LBEM_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(LBEM_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return LBEM_OK;
+    const int parity = int(b->t & 1);
+    if (!b->gexec || b->g_nsteps != nsteps || b->g_parity != parity || b->g_threads != b->threads ||
+        b->g_gpc != b->gpc) {
+        drop_graph(b);
+        // capture on a private stream (the null stream cannot be captured)
+        hipStream_t cs = nullptr;
+        lbem_status st = hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+        if (st) return st;
+        st = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (!st) {
+            launch_persistent(b, nsteps, cs);
+            hipGraph_t g = nullptr;
+            st = hip_check(hipStreamEndCapture(cs, &g), "end capture");
+            if (!st) {
+                b->graph = g;
+                st = hip_check(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0), "instantiate graph");
+            }
+        }
+        hipStreamDestroy(cs);
+        if (st) {
+            drop_graph(b);
+            return st;
+        }
+        b->g_nsteps = nsteps;
+        b->g_parity = parity;
+        b->g_threads = b->threads;
+        b->g_gpc = b->gpc;
+    }
+    lbem_status st = hip_check(hipGraphLaunch(b->gexec, b->stream), "graph launch");
+    if (!st) b->t += nsteps;
+    return st;
+}
+
+lbem_status lbem_batch_step_per_instance(lbem_batch *b, int64_t nsteps) {
+    if (!b) return fail(LBEM_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(LBEM_EINVAL, "nsteps < 0");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const BatchArgs a = args_of(b, 1);
+        const int odd = int(b->t & 1);
+        for (int32_t i = 0; i < b->n; ++i) {
+            const uint32_t s0 = uint32_t(b->off[i]), L = uint32_t(b->off[i + 1] - b->off[i]);
+            if (b->model == LBEM_MM) {
+                if (odd) launch_one_st<MM, 1>(b, a, s0, L);
+                else launch_one_st<MM, 0>(b, a, s0, L);
+            } else {
+                if (odd) launch_one_st<HV, 1>(b, a, s0, L);
+                else launch_one_st<HV, 0>(b, a, s0, L);
+            }
+        }
+        lbem_status st = hip_check(hipGetLastError(), "per-instance launch");
+        if (st) return st;
+        b->t += 1;
+    }
+    return LBEM_OK;
+}
+
+lbem_status lbem_batch_get_fields(lbem_batch *b, float *E, float *B) {
+    if (!b) return fail(LBEM_EINVAL, "batch is NULL");
+    const BatchArgs a = args_of(b, 0);
+    const int odd = int(b->t & 1);
+    if (b->model == LBEM_MM) {
+        if (odd) launch_fields_st<MM, 1>(b, a, E, B);
+        else launch_fields_st<MM, 0>(b, a, E, B);
+    } else {
+        if (odd) launch_fields_st<HV, 1>(b, a, E, B);
+        else launch_fields_st<HV, 0>(b, a, E, B);
+    }
+    return hip_check(hipGetLastError(), "fields launch");
+}
+
+lbem_status lbem_batch_get_time(lbem_batch *b, int64_t *t) {
+    if (!b || !t) return fail(LBEM_EINVAL, "null argument");
+    *t = b->t;
+    return LBEM_OK;
+}
+
+lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *threads, int32_t *groups_per_cu) {
+    if (!b) return fail(LBEM_EINVAL, "batch is NULL");
+    if (trial_steps < 1) return fail(LBEM_EINVAL, "trial_steps must be >= 1");
+    static const int32_t cand[][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}, {1024, 1}, {128, 4}, {128, 8}};
+    const size_t pb = b->L.backup - b->L.pop;
+    const int64_t t_saved = b->t;
+    lbem_status st = hip_check(hipMemcpyAsync(b->ws + b->L.backup, b->ws + b->L.pop, pb, hipMemcpyDeviceToDevice, b->stream), "backup");
+    if (st) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    st = hip_check(hipEventCreate(&e0), "event");
+    if (!st) st = hip_check(hipEventCreate(&e1), "event");
+    float best = 1e30f;
+    int32_t bt = b->threads, bg = b->gpc;
+    for (const auto &c : cand) {
+        if (st) break;
+        if (int64_t(c[1]) * b->ncu > kMaxGroups) continue;
+        st = lbem_batch_set_launch(b, c[0], c[1]);
+        if (st) break;
+        launch_persistent(b, 2, b->stream);  // warm-up
+        st = hip_check(hipEventRecord(e0, b->stream), "record");
+        if (!st) launch_persistent(b, trial_steps, b->stream);
+        if (!st) st = hip_check(hipEventRecord(e1, b->stream), "record");
+        if (!st) st = hip_check(hipEventSynchronize(e1), "sync");
+        float ms = 0.f;
+        if (!st) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        if (!st && ms < best) {
+            best = ms;
+            bt = c[0];
+            bg = c[1];
+        }
+        // restore the state for the next candidate
+        if (!st) st = hip_check(hipMemcpyAsync(b->ws + b->L.pop, b->ws + b->L.backup, pb, hipMemcpyDeviceToDevice, b->stream), "restore");
+        b->t = t_saved;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (st) return st;
+    st = lbem_batch_set_launch(b, bt, bg);
+    if (st) return st;
+    if (threads) *threads = bt;
+    if (groups_per_cu) *groups_per_cu = bg;
+    return LBEM_OK;
+}

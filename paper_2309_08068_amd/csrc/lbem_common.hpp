@@ -13,32 +13,56 @@ constexpr int kBlock = 256;  // threads per block of the lattice kernels (4 wave
 
 // ------------------------------------------------------------ storage formats
 // Populations live in HBM as FP32, BF16 or FP16; collision math is FP32.
+// raw<NT>() / put<NT>() move the stored representation (NT: non-temporal
+// hint, for streams that are touched once per step); cvt() / pack() convert.
+template <class T, bool NT>
+__device__ __forceinline__ T raw(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <class T, bool NT>
+__device__ __forceinline__ void put(T *p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 struct StF32 {
     using T = float;
     static constexpr int kBytes = 4;
-    __device__ static float load(const T *p, uint32_t i, float) { return p[i]; }
-    __device__ static void store(T *p, uint32_t i, float v, float) { p[i] = v; }
+    __device__ static float cvt(T r, float) { return r; }
+    __device__ static T pack(float v, float) { return v; }
+    template <bool NT = false>
+    __device__ static float load(const T *p, uint32_t i, float inv) { return cvt(raw<T, NT>(p + i), inv); }
+    template <bool NT = false>
+    __device__ static void store(T *p, uint32_t i, float v, float scale) { put<T, NT>(p + i, pack(v, scale)); }
 };
 
 struct StBF16 {
     using T = uint16_t;
     static constexpr int kBytes = 2;
-    __device__ static float load(const T *p, uint32_t i, float) { return __uint_as_float(uint32_t(p[i]) << 16); }
+    __device__ static float cvt(T r, float) { return __uint_as_float(uint32_t(r) << 16); }
     // round to nearest, ties to even (inputs are finite)
-    __device__ static uint16_t pack(float v) {
+    __device__ static T pack(float v, float) {
         uint32_t u = __float_as_uint(v);
         u += 0x7fffu + ((u >> 16) & 1u);
         return uint16_t(u >> 16);
     }
-    __device__ static void store(T *p, uint32_t i, float v, float) { p[i] = pack(v); }
+    template <bool NT = false>
+    __device__ static float load(const T *p, uint32_t i, float inv) { return cvt(raw<T, NT>(p + i), inv); }
+    template <bool NT = false>
+    __device__ static void store(T *p, uint32_t i, float v, float scale) { put<T, NT>(p + i, pack(v, scale)); }
 };
 
 struct StF16 {
     using T = _Float16;
     static constexpr int kBytes = 2;
     // values are held multiplied by a power-of-two scale
-    __device__ static float load(const T *p, uint32_t i, float inv_scale) { return float(p[i]) * inv_scale; }
-    __device__ static void store(T *p, uint32_t i, float v, float scale) { p[i] = _Float16(v * scale); }
+    __device__ static float cvt(T r, float inv_scale) { return float(r) * inv_scale; }
+    __device__ static T pack(float v, float scale) { return _Float16(v * scale); }
+    template <bool NT = false>
+    __device__ static float load(const T *p, uint32_t i, float inv) { return cvt(raw<T, NT>(p + i), inv); }
+    template <bool NT = false>
+    __device__ static void store(T *p, uint32_t i, float v, float scale) { put<T, NT>(p + i, pack(v, scale)); }
 };
 
 // ------------------------------------------------------------ addressing
@@ -77,7 +101,10 @@ __device__ __forceinline__ Nbr make_nbr(uint32_t c, uint32_t x, uint32_t y, uint
 //           post-collision value that x - v_q wrote during the previous step).
 // The step at an even t writes f'_q(x) to slot (opp q, x); at an odd t it
 // writes f'_q(x) to slot (q, x + v_q).  Each cell reads exactly the slots it
-// later writes, so the update is race-free without a second array.
+// later writes, so the update is race-free without a second array.  The
+// aligned even-parity accesses carry the non-temporal hint (each slot is
+// touched once per step); the shifted odd-parity accesses of this generic form
+// do not, because their cache lines are shared with neighbouring waves.
 template <class M, int ODD, class ST>
 __device__ __forceinline__ void gather(const typename ST::T *__restrict__ pop, size_t N, const Nbr &nb,
                                        float (&f)[M::Q], float inv_scale) {
@@ -87,7 +114,7 @@ __device__ __forceinline__ void gather(const typename ST::T *__restrict__ pop, s
             const uint32_t i = nb.at(-M::vel(q, 0), -M::vel(q, 1), -M::vel(q, 2));
             f[q] = ST::load(pop + size_t(M::opp(q)) * N, i, inv_scale);
         } else {
-            f[q] = ST::load(pop + size_t(q) * N, nb.c, inv_scale);
+            f[q] = ST::template load<true>(pop + size_t(q) * N, nb.c, inv_scale);
         }
     }
 }
@@ -101,15 +128,16 @@ __device__ __forceinline__ void scatter(typename ST::T *__restrict__ pop, size_t
             const uint32_t i = nb.at(M::vel(q, 0), M::vel(q, 1), M::vel(q, 2));
             ST::store(pop + size_t(q) * N, i, f[q], scale);
         } else {
-            ST::store(pop + size_t(M::opp(q)) * N, nb.c, f[q], scale);
+            ST::template store<true>(pop + size_t(M::opp(q)) * N, nb.c, f[q], scale);
         }
     }
 }
 
 // ------------------------------------------------------------ reductions
 // Sum of one double per thread over a block of kBlock threads, in a fixed
-// order (wavefront butterfly, then the four wave partials in order).  The
-// result is valid in thread 0.  `sm` is a __shared__ double[4].
+// order (wavefront butterfly, then the NW wave partials in order).  The
+// result is valid in thread 0.  `sm` is a __shared__ double[NW].
+template <int NW = kBlock / 64>
 __device__ __forceinline__ double block_sum(double v, double *sm) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -117,7 +145,8 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
     if (lane == 0) sm[wid] = v;
     __syncthreads();
     double r = 0.0;
-    if (threadIdx.x == 0) r = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NW; ++w) r += sm[w];
     return r;
 }
 

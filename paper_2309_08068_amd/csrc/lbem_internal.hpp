@@ -18,6 +18,10 @@ struct WsLayout {
 
 WsLayout layout(const lbem_desc *d);
 
+// x extent handled by the row form of the step kernel (one block per x-row),
+// or 0 when the lattice uses the generic form.
+uint32_t row_block(const lbem_desc *d);
+
 // Record a message for lbem_last_error and return st.
 lbem_status fail(lbem_status st, const char *fmt, ...);
 lbem_status hip_check(hipError_t e, const char *what);
@@ -25,4 +29,77 @@ lbem_status hip_check(hipError_t e, const char *what);
 // 2 pi n / period + phase with whole periods removed in double precision.
 double two_pi_frac(double n, double period, double phase);
 
+// Arguments of one launch of the 3-D step kernel.
+struct StepArgs {
+    void *pop;
+    const float *eps, *mu, *sig;
+    uint32_t nx, ny, nz, N;
+    float scale, inv_scale;
+    // soft current source: per-block ranges into a cell-sorted list
+    const int32_t *src_blk, *src_cell;
+    const float *src_J0;
+    float src_w;
+    // hard plane source
+    int32_t plane_z;
+    float Eimp[3], Bimp[3];
+    // probes: per-block ranges, cell, output slot; prb_row = this step's row
+    const int32_t *prb_blk, *prb_cell, *prb_slot;
+    double *prb_row;
+    // detector plane
+    int32_t det_z;
+    uint32_t det_b0, det_b1;
+    double *det_part;
+    // energy partials (null: not this step)
+    double *en_part;
+    // if set, E of the collided state is written here ([3][N] floats)
+    float *E_out;
+};
+
+
+}  // namespace lbem
+
+struct lbem_lattice {
+    lbem_desc d;
+    int Q;
+    size_t sbytes;
+    uint32_t N;
+    uint32_t bu;       // cells per step-kernel block and per table unit (nx in row form, else 256)
+    uint32_t nblocks;  // step-kernel blocks = table units, ceil(N / bu)
+    uint32_t nobs;     // blocks of the 256-thread observation kernels
+    float scale, inv_scale;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    lbem::WsLayout L;
+    // sources
+    int32_t nsrc;
+    double src_period, src_phase;
+    int32_t plane_z;
+    float pE0[3], pB0[3];
+    double plane_period;
+    // probes
+    int32_t nprobe;
+    int64_t prb_cap, prb_t0;
+    double *prb_series;
+    // detector
+    int32_t det_z;
+    uint32_t det_b0, det_b1;
+    // energy series
+    int32_t en_every;
+    int64_t en_cap, en_t0;
+    double *en_series;
+    int64_t t;
+    // adjoint session (lbem_adjoint_forward)
+    void *adj_ws;
+    int64_t adj_t0, adj_nsteps;
+    int32_t adj_K, adj_det;
+};
+
+
+namespace lbem {
+// Step-kernel arguments for the lattice's current configuration (no
+// observation or frame output set).
+StepArgs base_step_args(lbem_lattice *lat);
+// Launch one step kernel of the lattice's model and storage.
+void dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd);
 }  // namespace lbem

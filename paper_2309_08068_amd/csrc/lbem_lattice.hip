@@ -19,33 +19,11 @@
 #include "../../include/lbem.h"
 #include "lbem_common.hpp"
 #include "lbem_internal.hpp"
+#include "lbem_util_kernels.hpp"
 
 using namespace lbem;
 
 // ============================================================== kernels
-
-struct StepArgs {
-    void *pop;
-    const float *eps, *mu, *sig;
-    uint32_t nx, ny, nz, N;
-    float scale, inv_scale;
-    // soft current source: per-block ranges into a cell-sorted list
-    const int32_t *src_blk, *src_cell;
-    const float *src_J0;
-    float src_w;
-    // hard plane source
-    int32_t plane_z;
-    float Eimp[3], Bimp[3];
-    // probes: per-block ranges, cell, output slot; prb_row = this step's row
-    const int32_t *prb_blk, *prb_cell, *prb_slot;
-    double *prb_row;
-    // detector plane
-    int32_t det_z;
-    uint32_t det_b0, det_b1;
-    double *det_part;
-    // energy partials (null: not this step)
-    double *en_part;
-};
 
 template <class M, int ODD, class ST>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
@@ -82,6 +60,11 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     if (live) scatter<M, ODD, ST>(pop, N, nb, f, a.scale);
 
     // ---- observation of the state this step collided
+    if (a.E_out && live) {
+        a.E_out[c] = o.E[0];
+        a.E_out[N + c] = o.E[1];
+        a.E_out[2 * N + c] = o.E[2];
+    }
     if (a.prb_blk) {
         const int p0 = a.prb_blk[blk], p1 = a.prb_blk[blk + 1];
         for (int k = p0; k < p1; ++k)
@@ -107,10 +90,129 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     }
 }
 
+// Number of populations of M whose velocity has a non-zero x component.
+template <class M>
+constexpr int n_xshift() {
+    int n = 0;
+    for (int q = 0; q < M::Q; ++q) n += M::vel(q, 0) != 0;
+    return n;
+}
+
+// Row form of the step for lattices whose x extent equals the block (RB
+// threads = one full x-row; y and z are uniform per block).  Every HBM access
+// is a whole, aligned row segment with the non-temporal hint; the +-1 x shifts
+// of the odd parity go through LDS, which keeps partial cache lines out of the
+// memory traffic.  Same arithmetic as step_kernel, bit for bit.
+template <class M, int ODD, class ST, int RB>
+__global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
+    constexpr int NS = ODD ? n_xshift<M>() : 1;
+    constexpr int NW = RB / 64;
+    using T = typename ST::T;
+    __shared__ T sh[NS][RB];
+    __shared__ double sm_en[NW], sm_det[NW];
+    const uint32_t row = blockIdx.x;  // y + ny z
+    const uint32_t x = threadIdx.x;
+    const uint32_t y = row % a.ny, z = row / a.ny;
+    const uint32_t c = row * RB + x;
+    const size_t N = a.N;
+    T *pop = static_cast<T *>(a.pop);
+    const uint32_t yr[3] = {y == 0 ? a.ny - 1 : y - 1, y, y + 1 == a.ny ? 0 : y + 1};
+    const uint32_t zr[3] = {z == 0 ? a.nz - 1 : z - 1, z, z + 1 == a.nz ? 0 : z + 1};
+    auto rowoff = [&](int dy, int dz) -> uint32_t { return (yr[dy + 1] + a.ny * zr[dz + 1]) * RB; };
+
+    float f[M::Q];
+    if (!ODD) {
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q) f[q] = ST::template load<true>(pop + size_t(q) * N, c, a.inv_scale);
+    } else {
+        // f_q(x) = slot (opp q, x - v_q): load the aligned source row, shift x in LDS
+        int k = 0;
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q) {
+            const T *src = pop + size_t(M::opp(q)) * N + rowoff(-M::vel(q, 1), -M::vel(q, 2));
+            if (M::vel(q, 0) == 0) f[q] = ST::template load<true>(src, x, a.inv_scale);
+            else sh[k++][x] = raw<T, true>(src + x);
+        }
+        __syncthreads();
+        k = 0;
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q)
+            if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][(x + RB - M::vel(q, 0)) % RB], a.inv_scale);
+        __syncthreads();
+    }
+
+    CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
+    float Js[3] = {0.f, 0.f, 0.f};
+    if (a.src_blk) {
+        const int s0 = a.src_blk[row], s1 = a.src_blk[row + 1];
+        for (int k = s0; k < s1; ++k)
+            if (a.src_cell[k] == int32_t(c)) {
+                Js[0] = a.src_J0[3 * k] * a.src_w;
+                Js[1] = a.src_J0[3 * k + 1] * a.src_w;
+                Js[2] = a.src_J0[3 * k + 2] * a.src_w;
+            }
+    }
+    CellFields o;
+    Cell<M>::collide(f, m, Js, o);
+    if (int32_t(z) == a.plane_z) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
+
+    if (!ODD) {
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q) ST::template store<true>(pop + size_t(M::opp(q)) * N, c, f[q], a.scale);
+    } else {
+        // f'_q(x) goes to slot (q, x + v_q): shift x in LDS, store aligned rows
+        int k = 0;
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q) {
+            T *dst = pop + size_t(q) * N + rowoff(M::vel(q, 1), M::vel(q, 2));
+            if (M::vel(q, 0) == 0) ST::template store<true>(dst, x, f[q], a.scale);
+            else sh[k++][(x + M::vel(q, 0) + RB) % RB] = ST::pack(f[q], a.scale);
+        }
+        __syncthreads();
+        k = 0;
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q)
+            if (M::vel(q, 0) != 0) {
+                T *dst = pop + size_t(q) * N + rowoff(M::vel(q, 1), M::vel(q, 2));
+                put<T, true>(dst + x, sh[k++][x]);
+            }
+    }
+
+    // ---- observation of the state this step collided
+    if (a.E_out) {
+        a.E_out[c] = o.E[0];
+        a.E_out[N + c] = o.E[1];
+        a.E_out[2 * N + c] = o.E[2];
+    }
+    if (a.prb_blk) {
+        const int p0 = a.prb_blk[row], p1 = a.prb_blk[row + 1];
+        for (int k = p0; k < p1; ++k)
+            if (a.prb_cell[k] == int32_t(c)) {
+                double *o6 = a.prb_row + 6 * a.prb_slot[k];
+                o6[0] = o.E[0]; o6[1] = o.E[1]; o6[2] = o.E[2];
+                o6[3] = o.B[0]; o6[4] = o.B[1]; o6[5] = o.B[2];
+            }
+    }
+    if (a.det_part && row >= a.det_b0 && row <= a.det_b1) {
+        const double e2 = int32_t(z) == a.det_z
+                              ? double(o.E[0]) * o.E[0] + double(o.E[1]) * o.E[1] + double(o.E[2]) * o.E[2]
+                              : 0.0;
+        const double s = block_sum<NW>(e2, sm_det);
+        if (threadIdx.x == 0) a.det_part[row - a.det_b0] += s;
+    }
+    if (a.en_part) {
+        const double u = 0.5 * (double(o.E[0]) * o.D[0] + double(o.E[1]) * o.D[1] + double(o.E[2]) * o.D[2] +
+                                double(o.B[0]) * o.H[0] + double(o.B[1]) * o.H[1] + double(o.B[2]) * o.H[2]);
+        const double s = block_sum<NW>(u, sm_en);
+        if (threadIdx.x == 0) a.en_part[row] = s;
+    }
+}
+
 struct ObsArgs {
     const void *pop;
     const float *eps, *mu, *sig;
     uint32_t nx, ny, nz, N;
+    uint32_t bu;  // cells per source-table unit
     float inv_scale;
     const int32_t *src_blk, *src_cell;
     const float *src_J0;
@@ -136,7 +238,8 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
     CellMedia m{a.eps[cc], a.mu[cc], a.sig[cc]};
     float Js[3] = {0.f, 0.f, 0.f};
     if (a.src_blk) {
-        const int s0 = a.src_blk[blk], s1 = a.src_blk[blk + 1];
+        const uint32_t u = cc / a.bu;
+        const int s0 = a.src_blk[u], s1 = a.src_blk[u + 1];
         for (int k = s0; k < s1; ++k)
             if (a.src_cell[k] == int32_t(c)) {
                 Js[0] = a.src_J0[3 * k] * a.src_w;
@@ -179,42 +282,6 @@ __global__ __launch_bounds__(kBlock) void init_kernel(void *pop, const float *ep
     for (int q = 0; q < M::Q; ++q) ST::store(p + size_t(q) * N, c, f[q], scale);
 }
 
-// Fill a float array with a value, or copy src into it.
-__global__ void fill_or_copy(float *dst, const float *src, float value, uint32_t N) {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < N) dst[i] = src ? src[i] : value;
-}
-
-__global__ void zero_bytes(uint32_t *dst, size_t nwords) {
-    const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i < nwords) dst[i] = 0u;
-}
-
-// counts[0] non-finite, [1] non-positive eps/mu or negative sigma,
-// [2] eps mu < 1, [3] HV sigma / (3 eps) >= 2
-__global__ void validate_media(const float *eps, const float *mu, const float *sig, uint32_t N, int model,
-                               int32_t *counts) {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= N) return;
-    const float e = eps[i], m = mu[i], s = sig[i];
-    if (!isfinite(e) || !isfinite(m) || !isfinite(s)) {
-        atomicAdd(&counts[0], 1);
-        return;
-    }
-    if (!(e > 0.f) || !(m > 0.f) || s < 0.f) atomicAdd(&counts[1], 1);
-    else if (double(e) * double(m) < 1.0 - 1e-6) atomicAdd(&counts[2], 1);
-    if (model == LBEM_HV && s / (3.0f * e) >= 2.0f) atomicAdd(&counts[3], 1);
-}
-
-// Deterministic sum of n partials into out[0] (one block).
-__global__ __launch_bounds__(kBlock) void sum_partials(const double *part, uint32_t n, double *out) {
-    __shared__ double sm[4];
-    double s = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) s += part[i];
-    s = block_sum(s, sm);
-    if (threadIdx.x == 0) out[0] = s;
-}
-
 // ============================================================== host side
 
 namespace lbem {
@@ -233,36 +300,6 @@ lbem_status hip_check(hipError_t e, const char *what) {
     return fail(LBEM_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 }  // namespace lbem
-
-struct lbem_lattice {
-    lbem_desc d;
-    int Q;
-    size_t sbytes;
-    uint32_t N, nblocks;
-    float scale, inv_scale;
-    hipStream_t stream;
-    char *ws;
-    size_t ws_bytes;
-    WsLayout L;
-    // sources
-    int32_t nsrc;
-    double src_period, src_phase;
-    int32_t plane_z;
-    float pE0[3], pB0[3];
-    double plane_period;
-    // probes
-    int32_t nprobe;
-    int64_t prb_cap, prb_t0;
-    double *prb_series;
-    // detector
-    int32_t det_z;
-    uint32_t det_b0, det_b1;
-    // energy series
-    int32_t en_every;
-    int64_t en_cap, en_t0;
-    double *en_series;
-    int64_t t;
-};
 
 namespace {
 
@@ -290,10 +327,16 @@ size_t storage_bytes(int st) { return st == LBEM_F32 ? 4 : 2; }
 }  // namespace
 
 namespace lbem {
+uint32_t row_block(const lbem_desc *d) {
+    return (d->nx == 128 || d->nx == 256 || d->nx == 384 || d->nx == 512) ? uint32_t(d->nx) : 0u;
+}
+
 WsLayout layout(const lbem_desc *d) {
     WsLayout L;
     const size_t N = size_t(d->nx) * d->ny * d->nz;
-    const size_t nblocks = (N + kBlock - 1) / kBlock;
+    const size_t bu = row_block(d) ? row_block(d) : kBlock;
+    const size_t nblocks = (N + bu - 1) / bu;
+    const size_t nobs = (N + kBlock - 1) / kBlock;
     const size_t nxy = size_t(d->nx) * d->ny;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -305,8 +348,8 @@ WsLayout layout(const lbem_desc *d) {
     L.eps = take(N * 4);
     L.mu = take(N * 4);
     L.sig = take(N * 4);
-    L.en_part = take(nblocks * 8);
-    L.det_cap = nxy / kBlock + 2;
+    L.en_part = take(std::max(nblocks, nobs) * 8);
+    L.det_cap = nxy / bu + 2;
     L.det_part = take(L.det_cap * 8);
     L.src_blk = take((nblocks + 1) * 4);
     L.src_cell = take(size_t(LBEM_MAX_SOURCES) * 4);
@@ -360,7 +403,9 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     lat->Q = model_q(desc->model);
     lat->sbytes = storage_bytes(desc->storage);
     lat->N = uint32_t(size_t(desc->nx) * desc->ny * desc->nz);
-    lat->nblocks = grid_for(lat->N);
+    lat->bu = row_block(desc) ? row_block(desc) : uint32_t(kBlock);
+    lat->nblocks = uint32_t((size_t(lat->N) + lat->bu - 1) / lat->bu);
+    lat->nobs = grid_for(lat->N);
     lat->scale = (desc->storage == LBEM_F16 && desc->storage_scale != 0.0) ? float(desc->storage_scale) : 1.0f;
     lat->inv_scale = 1.0f / lat->scale;
     lat->stream = static_cast<hipStream_t>(stream);
@@ -418,7 +463,7 @@ lbem_status lbem_set_stream(lbem_lattice *lat, void *stream) {
 
 template <class M, class ST>
 static void launch_init(lbem_lattice *lat, const float *E, const float *B) {
-    hipLaunchKernelGGL((init_kernel<M, ST>), dim3(lat->nblocks), dim3(kBlock), 0, lat->stream, lat->ws + lat->L.pop,
+    hipLaunchKernelGGL((init_kernel<M, ST>), dim3(lat->nobs), dim3(kBlock), 0, lat->stream, lat->ws + lat->L.pop,
                        reinterpret_cast<const float *>(lat->ws + lat->L.eps),
                        reinterpret_cast<const float *>(lat->ws + lat->L.mu), E, B, lat->N, lat->scale);
 }
@@ -441,11 +486,11 @@ lbem_status lbem_set_fields(lbem_lattice *lat, const float *E, const float *B) {
 }
 
 // Build per-block [start, end) ranges into a cell-sorted list.
-static std::vector<int32_t> block_ranges(const std::vector<int32_t> &sorted_cells, uint32_t nblocks) {
+static std::vector<int32_t> block_ranges(const std::vector<int32_t> &sorted_cells, uint32_t nblocks, uint32_t bu) {
     std::vector<int32_t> r(nblocks + 1);
     size_t k = 0;
     for (uint32_t b = 0; b <= nblocks; ++b) {
-        const int64_t first = int64_t(b) * kBlock;
+        const int64_t first = int64_t(b) * bu;
         while (k < sorted_cells.size() && sorted_cells[k] < first) ++k;
         r[b] = int32_t(k);
     }
@@ -478,7 +523,7 @@ lbem_status lbem_set_current_source(lbem_lattice *lat, int32_t n, const int64_t 
         if (k && sc[k] == sc[k - 1]) return fail(LBEM_EINVAL, "source cell %d repeated", sc[k]);
         for (int a = 0; a < 3; ++a) sj[3 * k + a] = J0[3 * order[k] + a];
     }
-    std::vector<int32_t> br = block_ranges(sc, lat->nblocks);
+    std::vector<int32_t> br = block_ranges(sc, lat->nblocks, lat->bu);
     hipStream_t s = lat->stream;
     lbem_status st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_blk, br.data(), br.size() * 4, hipMemcpyHostToDevice, s), "copy");
     if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_cell, sc.data(), sc.size() * 4, hipMemcpyHostToDevice, s), "copy");
@@ -529,7 +574,7 @@ lbem_status lbem_set_probes(lbem_lattice *lat, int32_t n, const int64_t *cells, 
         pc[k] = int32_t(cells[order[k]]);
         ps[k] = order[k];
     }
-    std::vector<int32_t> br = block_ranges(pc, lat->nblocks);
+    std::vector<int32_t> br = block_ranges(pc, lat->nblocks, lat->bu);
     hipStream_t s = lat->stream;
     lbem_status st = hip_check(hipMemcpyAsync(lat->ws + lat->L.prb_blk, br.data(), br.size() * 4, hipMemcpyHostToDevice, s), "copy");
     if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.prb_cell, pc.data(), pc.size() * 4, hipMemcpyHostToDevice, s), "copy");
@@ -552,8 +597,8 @@ lbem_status lbem_set_detector(lbem_lattice *lat, int32_t z) {
     }
     const uint64_t nxy = uint64_t(lat->d.nx) * lat->d.ny;
     lat->det_z = z;
-    lat->det_b0 = uint32_t((uint64_t(z) * nxy) / kBlock);
-    lat->det_b1 = uint32_t((uint64_t(z + 1) * nxy - 1) / kBlock);
+    lat->det_b0 = uint32_t((uint64_t(z) * nxy) / lat->bu);
+    lat->det_b1 = uint32_t((uint64_t(z + 1) * nxy - 1) / lat->bu);
     const size_t words = size_t(lat->L.det_cap) * 2;
     hipLaunchKernelGGL(zero_bytes, dim3(grid_for(words)), dim3(kBlock), 0, lat->stream,
                        reinterpret_cast<uint32_t *>(lat->ws + lat->L.det_part), words);
@@ -583,20 +628,26 @@ lbem_status lbem_set_energy_series(lbem_lattice *lat, int32_t every, int64_t cap
 }
 
 template <class M, int ODD, class ST>
-static void launch_step(const StepArgs &a, uint32_t nblocks, hipStream_t s) {
-    hipLaunchKernelGGL((step_kernel<M, ODD, ST>), dim3(nblocks), dim3(kBlock), 0, s, a);
+static void launch_step(const StepArgs &a, uint32_t nblocks, uint32_t rb, hipStream_t s) {
+    switch (rb) {
+        case 128: hipLaunchKernelGGL((row_step_kernel<M, ODD, ST, 128>), dim3(nblocks), dim3(128), 0, s, a); break;
+        case 256: hipLaunchKernelGGL((row_step_kernel<M, ODD, ST, 256>), dim3(nblocks), dim3(256), 0, s, a); break;
+        case 384: hipLaunchKernelGGL((row_step_kernel<M, ODD, ST, 384>), dim3(nblocks), dim3(384), 0, s, a); break;
+        case 512: hipLaunchKernelGGL((row_step_kernel<M, ODD, ST, 512>), dim3(nblocks), dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL((step_kernel<M, ODD, ST>), dim3(nblocks), dim3(kBlock), 0, s, a); break;
+    }
 }
 
 template <class M, int ODD>
 static void dispatch_step_storage(const lbem_lattice *lat, const StepArgs &a) {
     switch (lat->d.storage) {
-        case LBEM_F32: launch_step<M, ODD, StF32>(a, lat->nblocks, lat->stream); break;
-        case LBEM_BF16: launch_step<M, ODD, StBF16>(a, lat->nblocks, lat->stream); break;
-        default: launch_step<M, ODD, StF16>(a, lat->nblocks, lat->stream); break;
+        case LBEM_F32: launch_step<M, ODD, StF32>(a, lat->nblocks, row_block(&lat->d), lat->stream); break;
+        case LBEM_BF16: launch_step<M, ODD, StBF16>(a, lat->nblocks, row_block(&lat->d), lat->stream); break;
+        default: launch_step<M, ODD, StF16>(a, lat->nblocks, row_block(&lat->d), lat->stream); break;
     }
 }
 
-static void dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd) {
+void lbem::dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd) {
     if (lat->d.model == LBEM_MM) {
         if (odd) dispatch_step_storage<MM, 1>(lat, a);
         else dispatch_step_storage<MM, 0>(lat, a);
@@ -614,9 +665,7 @@ double two_pi_frac(double n, double period, double phase) {
 }
 }  // namespace lbem
 
-lbem_status lbem_step(lbem_lattice *lat, int64_t nsteps) {
-    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
-    if (nsteps < 0) return fail(LBEM_EINVAL, "nsteps < 0");
+StepArgs lbem::base_step_args(lbem_lattice *lat) {
     const WsLayout &L = lat->L;
     StepArgs a{};
     a.pop = lat->ws + L.pop;
@@ -635,6 +684,15 @@ lbem_status lbem_step(lbem_lattice *lat, int64_t nsteps) {
         a.src_J0 = reinterpret_cast<const float *>(lat->ws + L.src_J0);
     }
     a.plane_z = lat->plane_z;
+    a.det_z = -1;
+    return a;
+}
+
+lbem_status lbem_step(lbem_lattice *lat, int64_t nsteps) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (nsteps < 0) return fail(LBEM_EINVAL, "nsteps < 0");
+    const WsLayout &L = lat->L;
+    StepArgs a = base_step_args(lat);
     if (lat->nprobe > 0) {
         a.prb_blk = reinterpret_cast<const int32_t *>(lat->ws + L.prb_blk);
         a.prb_cell = reinterpret_cast<const int32_t *>(lat->ws + L.prb_cell);
@@ -685,9 +743,9 @@ static void launch_obs(const ObsArgs &a, uint32_t nblocks, hipStream_t s) {
 template <class M, int ODD>
 static void dispatch_obs_storage(const lbem_lattice *lat, const ObsArgs &a) {
     switch (lat->d.storage) {
-        case LBEM_F32: launch_obs<M, ODD, StF32>(a, lat->nblocks, lat->stream); break;
-        case LBEM_BF16: launch_obs<M, ODD, StBF16>(a, lat->nblocks, lat->stream); break;
-        default: launch_obs<M, ODD, StF16>(a, lat->nblocks, lat->stream); break;
+        case LBEM_F32: launch_obs<M, ODD, StF32>(a, lat->nobs, lat->stream); break;
+        case LBEM_BF16: launch_obs<M, ODD, StBF16>(a, lat->nobs, lat->stream); break;
+        default: launch_obs<M, ODD, StF16>(a, lat->nobs, lat->stream); break;
     }
 }
 
@@ -702,6 +760,7 @@ static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, floa
     a.ny = lat->d.ny;
     a.nz = lat->d.nz;
     a.N = lat->N;
+    a.bu = lat->bu;
     a.inv_scale = lat->inv_scale;
     if (lat->nsrc > 0) {
         a.src_blk = reinterpret_cast<const int32_t *>(lat->ws + L.src_blk);
@@ -735,7 +794,7 @@ lbem_status lbem_energy(lbem_lattice *lat, double *out) {
     double *part = reinterpret_cast<double *>(lat->ws + lat->L.en_part);
     lbem_status st = observe(lat, nullptr, nullptr, nullptr, nullptr, part);
     if (st) return st;
-    hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream, part, lat->nblocks, out);
+    hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream, part, lat->nobs, out);
     return hip_check(hipGetLastError(), "energy sum");
 }
 

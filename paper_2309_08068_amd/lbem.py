@@ -45,6 +45,20 @@ SIGNATURES = {
     "lbem_energy": (_I32, [_P, _P]),
     "lbem_save_state": (_I32, [_P, _P]),
     "lbem_load_state": (_I32, [_P, _P, _I64]),
+    "lbem_adjoint_workspace_size": (_I32, [_P, _I64, _I32, C.POINTER(_SZ)]),
+    "lbem_adjoint_forward": (_I32, [_P, _I64, _I32, _I32, _P, _SZ, _P]),
+    "lbem_adjoint_backward": (_I32, [_P, _P, _SZ, _P, _P, _D, _P, _P]),
+    "lbem_batch_workspace_size": (_I32, [_I32, _I32, _I32, _P, C.POINTER(_SZ)]),
+    "lbem_batch_create": (_I32, [_I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P, C.POINTER(_P)]),
+    "lbem_batch_destroy": (_I32, [_P]),
+    "lbem_batch_set_fields": (_I32, [_P, _P, _P]),
+    "lbem_batch_set_launch": (_I32, [_P, _I32, _I32]),
+    "lbem_batch_autotune": (_I32, [_P, _I32, C.POINTER(_I32), C.POINTER(_I32)]),
+    "lbem_batch_step": (_I32, [_P, _I64]),
+    "lbem_batch_step_graph": (_I32, [_P, _I64]),
+    "lbem_batch_step_per_instance": (_I32, [_P, _I64]),
+    "lbem_batch_get_fields": (_I32, [_P, _P, _P]),
+    "lbem_batch_get_time": (_I32, [_P, C.POINTER(_I64)]),
 }
 
 
@@ -241,6 +255,110 @@ class Lattice:
         if src.numel() * src.element_size() < self.state_size():
             raise ValueError("state buffer too small")
         check(self.lib.lbem_load_state(self.h, _ptr(src), int(t)))
+
+    # ------------------------------------------------------------ adjoint
+    def adjoint_workspace(self, nsteps: int, K: int) -> torch.Tensor:
+        size = C.c_size_t()
+        check(self.lib.lbem_adjoint_workspace_size(C.byref(self._desc), int(nsteps), int(K), C.byref(size)))
+        return torch.empty(size.value, dtype=torch.uint8, device=self.device)
+
+    def adjoint_forward(self, nsteps: int, K: int, det_z: int, ws: torch.Tensor) -> torch.Tensor:
+        """Run nsteps with a checkpoint every K steps; return the detector loss (dev double [1])."""
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        check(self.lib.lbem_adjoint_forward(self.h, int(nsteps), int(K), int(det_z), _ptr(ws),
+                                            ws.numel(), _ptr(loss)))
+        return loss
+
+    def adjoint_backward(self, ws: torch.Tensor, E0=None, B0=None, scale: float = 1.0):
+        """dL/deps_r and dL/dsigma (dev double [N]) for the last adjoint_forward."""
+        ge = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        gs = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        E0 = _dev_f32(E0, 3 * self.n, self.device)
+        B0 = _dev_f32(B0, 3 * self.n, self.device)
+        check(self.lib.lbem_adjoint_backward(self.h, _ptr(ws), ws.numel(), _ptr(E0), _ptr(B0), float(scale),
+                                             _ptr(ge), _ptr(gs)))
+        self._keep["adjoint_fields0"] = (E0, B0)
+        return ge, gs
+
+
+class Batch:
+    """Many independent ragged 1-D lattices (1 x 1 x L_b) advanced together."""
+
+    def __init__(self, model: str, offsets, eps_r=None, mu_r=None, sigma=None, storage: str = "f32",
+                 device="cuda", stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the lbem library needs a GPU; none is visible")
+        self.lib = load_library()
+        self.model, self.storage = model, storage
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.n = len(self.offsets) - 1
+        self.total = int(self.offsets[-1])
+        self.device = torch.device(device)
+        size = C.c_size_t()
+        op = self.offsets.ctypes.data_as(C.c_void_p)
+        check(self.lib.lbem_batch_workspace_size(MODEL[model], STORAGE[storage], self.n, op, C.byref(size)))
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        media = [_dev_f32(x, self.total, self.device) for x in (eps_r, mu_r, sigma)]
+        h = C.c_void_p()
+        check(self.lib.lbem_batch_create(MODEL[model], STORAGE[storage], self.n, op, *[_ptr(m) for m in media],
+                                         _ptr(self.workspace), size.value, C.c_void_p(_stream_ptr(stream)),
+                                         C.byref(h)))
+        self.h = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbem_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_fields(self, E, B):
+        E = _dev_f32(E, 3 * self.total, self.device)
+        B = _dev_f32(B, 3 * self.total, self.device)
+        check(self.lib.lbem_batch_set_fields(self.h, _ptr(E), _ptr(B)))
+        self._keep = (E, B)
+
+    def set_launch(self, threads: int, groups_per_cu: int):
+        check(self.lib.lbem_batch_set_launch(self.h, int(threads), int(groups_per_cu)))
+
+    def autotune(self, trial_steps: int = 20):
+        t, g = C.c_int32(), C.c_int32()
+        check(self.lib.lbem_batch_autotune(self.h, int(trial_steps), C.byref(t), C.byref(g)))
+        return t.value, g.value
+
+    def step(self, nsteps: int):
+        check(self.lib.lbem_batch_step(self.h, int(nsteps)))
+
+    def step_graph(self, nsteps: int):
+        check(self.lib.lbem_batch_step_graph(self.h, int(nsteps)))
+
+    def step_per_instance(self, nsteps: int):
+        check(self.lib.lbem_batch_step_per_instance(self.h, int(nsteps)))
+
+    @property
+    def time(self) -> int:
+        t = C.c_int64()
+        check(self.lib.lbem_batch_get_time(self.h, C.byref(t)))
+        return t.value
+
+    def fields(self):
+        """(E, B), each a [3][total] float32 device tensor."""
+        E = torch.empty((3, self.total), dtype=torch.float32, device=self.device)
+        B = torch.empty((3, self.total), dtype=torch.float32, device=self.device)
+        check(self.lib.lbem_batch_get_fields(self.h, _ptr(E), _ptr(B)))
+        return E, B
+
+
+def batch_from_inputs(bt, storage: str = "f32") -> Batch:
+    """Set up a Batch from an inputs.Batch (media and initial fields)."""
+    b = Batch(bt.model, bt.offsets, bt.eps_r, bt.mu_r, bt.sigma, storage=storage)
+    b.set_fields(bt.E0, bt.B0)
+    return b
 
 
 def lattice_from_workload(w, storage: str = "f32", storage_scale: float = 0.0) -> Lattice:

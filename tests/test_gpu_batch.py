@@ -1,0 +1,125 @@
+"""GPU parity of the batched ragged 1-D stepper against the FP64 CPU oracle:
+every instance must equal the oracle run of its own 1 x 1 x L lattice, and the
+persistent launch, its HIP graph and the one-launch-per-instance schedule must
+agree bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2309_08068_amd import inputs, lbem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def oracle_instance(model, eps, mu, sig, E0, B0, steps, real="f64"):
+    L = len(eps)
+    P = oracle.Problem(model, (1, 1, L), eps_r=eps, mu_r=mu, sigma=sig)
+    f = oracle.init(P, E0, B0, real=real)
+    oracle.run(P, f, 0, steps)
+    E, B, _, _ = oracle.fields(P, f, steps)
+    return E, B
+
+
+def random_batch(seed, lengths):
+    rng = np.random.default_rng(seed)
+    off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    tot = int(off[-1])
+    return dict(off=off, eps=rng.uniform(1, 3, tot), mu=rng.uniform(1, 2, tot), sig=rng.uniform(0, 0.2, tot),
+                E0=rng.normal(size=(3, tot)), B0=rng.normal(size=(3, tot)))
+
+
+@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("storage", ["f32"])
+def test_batch_random_parity_and_schedules(model, storage):
+    lengths = [1, 2, 3, 17, 64, 65, 255, 256, 257, 700, 1031, 5]
+    d = random_batch(42, lengths)
+    steps = 9
+    outs = {}
+    for sched in ("persistent", "graph", "per_instance"):
+        b = lbem.Batch(model, d["off"], d["eps"], d["mu"], d["sig"], storage=storage)
+        b.set_launch(128, 1)
+        b.set_fields(d["E0"], d["B0"])
+        if sched == "persistent":
+            b.step(4)
+            b.step(5)
+        elif sched == "graph":
+            b.step_graph(4)
+            b.step_graph(5)
+        else:
+            b.step_per_instance(9)
+        assert b.time == steps
+        E, B = b.fields()
+        torch.cuda.synchronize()
+        outs[sched] = (E.cpu().numpy(), B.cpu().numpy())
+    for sched in ("graph", "per_instance"):
+        assert np.array_equal(outs[sched][0], outs["persistent"][0]), sched
+        assert np.array_equal(outs[sched][1], outs["persistent"][1]), sched
+    E, B = (x.astype(np.float64) for x in outs["persistent"])
+    for i in range(len(lengths)):
+        s, e = d["off"][i], d["off"][i + 1]
+        Eo, Bo = oracle_instance(model, d["eps"][s:e], d["mu"][s:e], d["sig"][s:e], d["E0"][:, s:e], d["B0"][:, s:e],
+                                 steps)
+        assert rel(E[:, s:e], Eo) < TOL, (i, rel(E[:, s:e], Eo))
+        assert rel(B[:, s:e], Bo) < TOL, (i, rel(B[:, s:e], Bo))
+
+
+def test_batch_autotune_leaves_state_unchanged():
+    d = random_batch(7, [300, 5000, 1200, 64] * 8)
+    b = lbem.Batch("mm", d["off"], d["eps"], d["mu"], d["sig"])
+    b.set_fields(d["E0"], d["B0"])
+    b.step(3)
+    E0, _ = b.fields()
+    E0 = E0.clone()
+    threads, gpc = b.autotune(4)
+    assert threads in (128, 256, 512, 1024) and gpc >= 1
+    assert b.time == 3
+    E1, _ = b.fields()
+    assert torch.equal(E0, E1)
+
+
+@pytest.mark.parametrize("model", ["mm"])
+def test_multilayer_workload_sampled_parity(model):
+    """The full multilayer workload (512 instances, lengths 500..8000, 5000
+    steps) in the autotuned launch configuration the benchmark times; the
+    shortest, the longest and two random instances are compared with the
+    oracle run of each instance.  MM only: HV grows an interface mode at
+    every layer boundary (see the oracle's spectral test)."""
+    bt = inputs.multilayer(model, steps=5000)
+    b = lbem.batch_from_inputs(bt)
+    b.autotune(10)
+    b.step(bt.steps)
+    E, B = b.fields()
+    E = E.double().cpu().numpy()
+    B = B.double().cpu().numpy()
+    L = bt.lengths
+    rng = np.random.default_rng(3)
+    pick = {int(np.argmin(L)), int(np.argmax(L)), *map(int, rng.choice(len(L), 2, replace=False))}
+    for i in sorted(pick):
+        w = bt.instance(i)
+        Eo, Bo = oracle_instance(model, w.eps_r, w.mu_r, w.sigma, w.E0, w.B0, bt.steps)
+        Ef, Bf = oracle_instance(model, w.eps_r, w.mu_r, w.sigma, w.E0, w.B0, bt.steps, real="f32")
+        floor = max(rel(Ef, Eo), rel(Bf, Bo))
+        tol = max(TOL, 2 * floor)
+        s, e = bt.offsets[i], bt.offsets[i + 1]
+        print(f"instance {i} (L={e - s}): float32 floor {floor:.2e}, GPU error "
+              f"{rel(E[:, s:e], Eo):.2e} / {rel(B[:, s:e], Bo):.2e}", flush=True)
+        assert rel(E[:, s:e], Eo) < tol
+        assert rel(B[:, s:e], Bo) < tol
+
+
+def test_batch_rejects_bad_offsets_and_media():
+    with pytest.raises(lbem.LbemError):
+        lbem.Batch("mm", [0, 5, 5, 9])
+    with pytest.raises(lbem.LbemError):
+        lbem.Batch("mm", [1, 5])
+    with pytest.raises(lbem.LbemError) as e:
+        lbem.Batch("mm", [0, 4], eps_r=np.full(4, 0.5))
+    assert e.value.status == -4

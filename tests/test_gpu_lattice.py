@@ -74,7 +74,10 @@ def run_oracle(model, shape, p, steps, real="f64", probes=None, det_z=None, ener
     return out
 
 
-SHAPES = [(1, 1, 17), (7, 5, 9), (16, 16, 16), (33, 3, 5), (300, 1, 1), (1, 40, 1), (9, 1, 31)]
+# generic form (odd sizes, ragged last block, axes of length 1) and the row form
+# (x extent 128, 256, 384 or 512: one block per x-row, LDS x-shifts)
+SHAPES = [(1, 1, 17), (7, 5, 9), (16, 16, 16), (33, 3, 5), (300, 1, 1), (1, 40, 1), (9, 1, 31),
+          (128, 3, 5), (256, 2, 3), (384, 1, 2), (512, 2, 1)]
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
@@ -93,12 +96,14 @@ def test_random_state_parity(model, shape, steps):
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
-def test_observations_parity(model):
-    """Probe series, energy series and detector-plane accumulation (FP64 on both sides)."""
-    shape = (12, 10, 14)
+@pytest.mark.parametrize("shape", [(12, 10, 14), (128, 6, 14)])
+def test_observations_parity(model, shape):
+    """Probe series, energy series and detector-plane accumulation (FP64 on both
+    sides), in the generic and the row form of the step kernel."""
     steps = 30
     p = random_problem(model, shape, seed=5)
-    probes = [0, 17, 12 * 10 * 7 + 5, 12 * 10 * 14 - 1]
+    n = int(np.prod(shape))
+    probes = [0, 17, shape[0] * shape[1] * 7 + 5, n - 1]
     g, _ = run_gpu(model, shape, p, steps, probes=probes, det_z=6, energy_every=4)
     o = run_oracle(model, shape, p, steps, probes=probes, det_z=6, energy_every=4)
     assert rel(g["probes"], o["probes"]) < TOL
@@ -107,8 +112,8 @@ def test_observations_parity(model):
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
-def test_energy_call_matches_oracle(model):
-    shape = (6, 7, 8)
+@pytest.mark.parametrize("shape", [(6, 7, 8), (128, 3, 4)])
+def test_energy_call_matches_oracle(model, shape):
     p = random_problem(model, shape, seed=11)
     _, lat = run_gpu(model, shape, p, 5)
     u = lat.energy().item()
@@ -191,8 +196,8 @@ def test_dipole_light_cone_and_symmetry_long_run(model):
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
-def test_save_load_and_determinism(model):
-    shape = (10, 9, 8)
+@pytest.mark.parametrize("shape", [(10, 9, 8), (128, 4, 5)])
+def test_save_load_and_determinism(model, shape):
     p = random_problem(model, shape, seed=3)
     lat = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"])
     lat.set_fields(p["E0"], p["B0"])
@@ -220,15 +225,16 @@ def test_save_load_and_determinism(model):
 def test_low_precision_storage_bound(model, storage, bound):
     """BF16 / FP16 population storage with FP32 collision: the error against the
     FP64 oracle stays within the stated bound on a smooth 3-D wave (no bit-level
-    parity is expected; the bound is a property of the format)."""
-    shape = (32, 32, 32)
-    c = inputs.VACUUM_SPEED[model]
-    E0, B0 = inputs.gaussian_pulse(shape, 12.0, 4.0, c)
-    p = dict(eps=np.full(32 ** 3, 1.5), mu=None, sig=None, E0=E0, B0=B0)
-    g, _ = run_gpu(model, shape, p, 100, storage=storage, scale=256.0 if storage == "f16" else 0.0)
-    o = run_oracle(model, shape, p, 100)
-    for k in "EB":
-        assert rel(g[k], o[k]) < bound, (k, rel(g[k], o[k]))
+    parity is expected; the bound is a property of the format), in the generic
+    and the row form."""
+    for shape in ((32, 32, 32), (128, 8, 32)):
+        c = inputs.VACUUM_SPEED[model]
+        E0, B0 = inputs.gaussian_pulse(shape, 12.0, 4.0, c)
+        p = dict(eps=np.full(int(np.prod(shape)), 1.5), mu=None, sig=None, E0=E0, B0=B0)
+        g, _ = run_gpu(model, shape, p, 100, storage=storage, scale=256.0 if storage == "f16" else 0.0)
+        o = run_oracle(model, shape, p, 100)
+        for k in "EB":
+            assert rel(g[k], o[k]) < bound, (shape, k, rel(g[k], o[k]))
 
 
 def test_unstable_and_invalid_media_rejected():

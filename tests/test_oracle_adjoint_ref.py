@@ -1,0 +1,58 @@
+"""Pins of the FP64 automatic-differentiation reference used to check the
+adjoint: its forward equals the C oracle, and its gradient equals central
+finite differences of its own loss (FP64, second order)."""
+import numpy as np
+import torch
+
+import oracle
+from oracle import torch_ref as tr
+
+
+def random_case(shape, seed):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    d = dict(eps=rng.uniform(1, 3, N), mu=rng.uniform(1, 2, N), sig=rng.uniform(0, 0.2, N),
+             E0=rng.normal(size=(3, N)), B0=rng.normal(size=(3, N)))
+    T = lambda a: torch.tensor(a.reshape(-1, nz, ny, nx) if a.ndim == 2 else a.reshape(nz, ny, nx))
+    return d, {k: T(v) for k, v in d.items()}
+
+
+def test_torch_reference_equals_c_oracle():
+    shape = (4, 3, 6)
+    d, t = random_case(shape, 0)
+    P = oracle.Problem("mm", shape, eps_r=d["eps"], mu_r=d["mu"], sigma=d["sig"])
+    f = oracle.init(P, d["E0"], d["B0"])
+    out = oracle.run(P, f, 0, 7, det_z=2)
+    E, B, _, _ = oracle.fields(P, f, 7)
+    L, ft = tr.detector_loss(t["eps"], t["sig"], t["mu"], t["E0"], t["B0"], 7, 2)
+    Et, Bt = tr.fields(ft, t["eps"], t["mu"], t["sig"])
+    np.testing.assert_allclose(Et.numpy().reshape(3, -1), E, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(Bt.numpy().reshape(3, -1), B, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(L.item(), out["detector"].sum(), rtol=1e-12)
+
+
+def test_torch_reference_gradient_equals_finite_differences():
+    shape = (3, 2, 5)
+    d, t = random_case(shape, 1)
+    eps = t["eps"].clone().requires_grad_(True)
+    sig = t["sig"].clone().requires_grad_(True)
+    L, _ = tr.detector_loss(eps, sig, t["mu"], t["E0"], t["B0"], 6, 3)
+    ge, gs = torch.autograd.grad(L, (eps, sig))
+    h = 1e-5
+    rng = np.random.default_rng(2)
+    for _ in range(6):
+        k = tuple(int(rng.integers(0, s)) for s in eps.shape)
+        for g, which in ((ge, "eps"), (gs, "sig")):
+            ap, am = t["eps"].clone(), t["eps"].clone()
+            sp, sm = t["sig"].clone(), t["sig"].clone()
+            if which == "eps":
+                ap[k] += h
+                am[k] -= h
+            else:
+                sp[k] += h
+                sm[k] -= h
+            Lp, _ = tr.detector_loss(ap, sp, t["mu"], t["E0"], t["B0"], 6, 3)
+            Lm, _ = tr.detector_loss(am, sm, t["mu"], t["E0"], t["B0"], 6, 3)
+            fd = (Lp - Lm).item() / (2 * h)
+            assert abs(fd - g[k].item()) <= 1e-6 * max(1.0, abs(fd)), (which, k, fd, g[k].item())
