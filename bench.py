@@ -64,6 +64,7 @@ def time_variant(model: str, storage: str, n: int, steps: int, warmup: int):
     w = inputs.dipole(model, n=n, steps=steps)
     lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=0.0)
     lat.set_probes(w.probes, warmup + 2 * steps + 1)
+    tuning = lat.autotune(10)
     stream = torch.cuda.current_stream()
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -88,7 +89,73 @@ def time_variant(model: str, storage: str, n: int, steps: int, warmup: int):
     torch.cuda.empty_cache()
     return dict(model=model, storage=storage, cells=cells, mlups=mlups, ms_per_step=wall * 1e3 / steps,
                 kernel_ms=kernel_ms, bytes_per_lu=bpl, achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS,
-                traffic=measured_traffic(model, storage, cells))
+                traffic=measured_traffic(model, storage, cells), tuning=tuning)
+
+
+def time_batch(steps: int):
+    """Multilayer workload: 512 ragged 1-D MM instances (500..8000 cells), FP32.
+    One persistent launch captured in a HIP graph (autotuned launch shape) versus
+    one launch per instance per step (timed on a sample of steps)."""
+    import torch
+    from paper_2309_08068_amd import inputs, lbem
+
+    bt = inputs.multilayer("mm", steps=steps)
+    b = lbem.batch_from_inputs(bt)
+    threads, gpc = b.autotune(10)
+    total = int(bt.offsets[-1])
+    b.step_graph(steps)  # capture + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step_graph(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sample = 20
+    b.step_per_instance(2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b.step_per_instance(sample)
+    torch.cuda.synchronize()
+    wall_pi = (time.perf_counter() - t1) / sample * steps
+    mlups = total * steps / wall / 1e6
+    bpl = BYTES_PER_LU[("mm", "f32")]
+    return {"workload": f"multilayer_512x[500,8000]_{steps}steps", "cells": total, "launch": [threads, gpc],
+            "persistent_graph_s": round(wall, 4), "mlups": round(mlups, 1),
+            "achieved_gbs": round(bpl * total * steps / wall / 1e9, 1),
+            "frac": round(bpl * total * steps / wall / 1e9 / HBM_PEAK_GBS, 4),
+            "per_instance_loop_s": round(wall_pi, 3), "per_instance_sample_steps": sample,
+            "speedup_vs_per_instance": round(wall_pi / wall, 1)}
+
+
+def time_adjoint(model: str, steps: int, K: int, keep: int):
+    """Inverse-design lattice 128 x 128 x 256 (FP32): adjoint pass (forward with
+    a checkpoint every K steps, the last `keep` segments also keeping their E
+    frames, + reverse pass) over the plain forward with the same detector."""
+    import torch
+    from paper_2309_08068_amd import inputs, lbem
+
+    w = inputs.slab(model, steps=steps)
+    lat = lbem.lattice_from_workload(w)
+    lat.autotune(5)
+    lat.step(5)
+    lat.set_fields(*w.fields0())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    lat.set_fields(*w.fields0())
+    ws = lat.adjoint_workspace(steps, K, keep)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.adjoint_forward(steps, K, w.det_z, ws, keep)
+    ge, gs = lat.adjoint_backward(ws, *w.fields0())
+    torch.cuda.synchronize()
+    adj = time.perf_counter() - t1
+    ok = bool(torch.isfinite(ge).all() and torch.isfinite(gs).all())
+    del ws
+    torch.cuda.empty_cache()
+    return {"workload": f"slab_128x128x256_{model}_{steps}steps_K{K}_keep{keep}", "forward_s": round(fwd, 4),
+            "adjoint_total_s": round(adj, 4), "ratio": round(adj / fwd, 3), "finite_gradients": ok}
 
 
 def cpu_baseline(n: int, sample_steps: int):
@@ -116,6 +183,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--only", default="", help="comma list of model_storage variants to time")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=1500)
+    ap.add_argument("--profile", action="store_true",
+                    help="for rocprofv3 counter runs: only `steps` steps of the --only variants, then a plain "
+                         "copy of 1 GiB (torch copy_) three times as the calibration kernel of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
@@ -130,12 +204,30 @@ def main():
     if args.only:
         keep = set(args.only.split(","))
         variants = [v for v in variants if f"{v[0]}_{v[1]}" in keep]
+    if args.profile:
+        from paper_2309_08068_amd import inputs, lbem
+        for model, storage in variants:
+            w = inputs.dipole(model, n=args.n, steps=args.steps)
+            lat = lbem.lattice_from_workload(w, storage=storage)
+            lat.set_probes(w.probes, args.steps + 1)
+            lat.step(args.steps)
+            torch.cuda.synchronize()
+            print(f"# profiled {args.steps} steps of {model} {storage}", file=sys.stderr, flush=True)
+            del lat
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# calibration copy: 1 GiB read + 1 GiB written per launch, 3 launches", file=sys.stderr, flush=True)
+        return
     results = {}
     for model, storage in variants:
         r = time_variant(model, storage, args.n, args.steps, args.warmup)
         results[f"{model}_{storage}"] = r
         print(f"# {model} {storage}: {r['mlups']:.0f} MLUPS, step kernel {r['kernel_ms']:.3f} ms, "
-              f"{r['achieved_gbs']:.0f} GB/s ({100 * r['frac']:.1f}% of peak)", file=sys.stderr, flush=True)
+              f"{r['achieved_gbs']:.0f} GB/s ({100 * r['frac']:.1f}% of peak), tuning {r['tuning']}",
+              file=sys.stderr, flush=True)
     head = results.get("mm_f32") or next(iter(results.values()))
     traffic = head["traffic"]
     line = {
@@ -161,9 +253,22 @@ def main():
                      "bytes_per_lu": head["bytes_per_lu"], "kernel_ms": round(head["kernel_ms"], 4)},
         "variants": {k: {"mlups": round(v["mlups"], 1), "achieved_gbs": round(v["achieved_gbs"], 1),
                          "frac": round(v["frac"], 4), "kernel_ms": round(v["kernel_ms"], 4),
-                         "bytes_per_lu": v["bytes_per_lu"]} for k, v in results.items()},
+                         "bytes_per_lu": v["bytes_per_lu"], "tuning": v["tuning"]} for k, v in results.items()},
         "adjoint_over_forward": None,
     }
+    if not args.no_batch:
+        line["batched_1d"] = time_batch(args.batch_steps)
+        print(f"# batched 1-D: {line['batched_1d']}", file=sys.stderr, flush=True)
+    if not args.no_adjoint:
+        # HV is the model whose run stays bounded on this smooth 3-D medium;
+        # keep = 1 is the minimal-memory schedule (every segment but the last is
+        # recomputed), keep = 10 holds 10 segments of frames (25 GB) in HBM
+        runs = [time_adjoint("hv", args.adjoint_steps, 50, 1), time_adjoint("hv", args.adjoint_steps, 50, 10),
+                time_adjoint("mm", args.adjoint_steps, 50, 1)]
+        line["adjoint"] = runs
+        line["adjoint_over_forward"] = runs[0]["ratio"]
+        for r in runs:
+            print(f"# adjoint: {r}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -158,6 +158,21 @@ lbem_status lbem_get_fields(lbem_lattice *lat, float *E, float *B, float *D, flo
 /* U = 1/2 sum over cells of (E.D + B.H) of the current state -> out (dev double [1]). */
 lbem_status lbem_energy(lbem_lattice *lat, double *out);
 
+/* Launch tuning of the step kernel, per parity (index 0 even, 1 odd time
+ * level): form[p] in {0, 1} selects one of two equivalent address forms of
+ * the row kernel (1: store addresses formed after the collision, which lowers
+ * register use), blocks_per_cu[p] caps the blocks resident per compute unit
+ * (0: no cap; implemented with unused dynamic LDS).  Results are bit-identical
+ * for every choice; only the speed differs.  create() sets measured defaults. */
+lbem_status lbem_set_tuning(lbem_lattice *lat, const int32_t *form, const int32_t *blocks_per_cu);
+lbem_status lbem_get_tuning(lbem_lattice *lat, int32_t *form, int32_t *blocks_per_cu);
+
+/* Time every (form, cap) candidate for each parity over trial_steps launches
+ * and keep the fastest.  backup: dev, lbem_state_size bytes; the state is
+ * copied there first and restored afterwards, so the lattice is unchanged.
+ * Synchronises the stream. */
+lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup);
+
 /* Copy the population state to dst (dev, lbem_state_size bytes) / restore it
  * together with the time level it was saved at (get it with lbem_get_time). */
 lbem_status lbem_save_state(lbem_lattice *lat, void *dst);
@@ -176,20 +191,25 @@ lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t);
  * Memory: the forward stores a checkpoint every K steps; the backward
  * recomputes each segment storing E(f_n) per step (FP32 frames), then runs
  * the segment's adjoint steps in reverse (in-place AA streaming with reversed
- * velocities).  Gradients accumulate in FP64.  Model MM only (HV has a
- * growing interface mode, which makes its gradients meaningless over long
- * runs); no soft or hard sources may be set.
+ * velocities).  Gradients accumulate in FP32 over a segment and in FP64
+ * across segments.  Both models; no soft or hard sources may be set.
  * ------------------------------------------------------------------------ */
 
-/* Bytes of adjoint workspace for nsteps steps with a checkpoint every K. */
-lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, int32_t K, size_t *bytes);
+/* Bytes of adjoint workspace for nsteps steps with a checkpoint every K steps,
+ * of which the last `keep` segments (>= 1) also hold their per-step E frames
+ * (3 N floats per step) so that the reverse pass does not recompute them:
+ * keep trades HBM for recomputation, keep = ceil(nsteps / K) recomputes nothing. */
+lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, int32_t K, int32_t keep,
+                                        size_t *bytes);
 
 /* Run nsteps steps from the current state (time level t0) recording
  * checkpoints in ws, and write L (sum over the collided states of the plane
  * det_z of |E|^2, FP64) to loss (dev double [1]).  Leaves the lattice at
- * t0 + nsteps.  LBEM_ESTATE if sources are set or the model is not MM. */
-lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t det_z, void *ws,
-                                 size_t ws_bytes, double *loss);
+ * t0 + nsteps.  The last `keep` segments also keep E(f_n) of each of their
+ * steps in ws, so the reverse pass recomputes only the earlier segments.
+ * LBEM_ESTATE if sources are set. */
+lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z,
+                                 void *ws, size_t ws_bytes, double *loss);
 
 /* Reverse pass for the last lbem_adjoint_forward with this ws: writes
  * dL/deps_r and dL/dsigma (dev double [N]) times `scale`.  If E0 and B0 (dev

@@ -36,7 +36,7 @@ def build(force: bool = True) -> None:
         out = os.path.join(HERE, f"liboracle{tag}.so")
         if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
             continue
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", f"-DORACLE_REAL={real}",
+        cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", f"-DORACLE_REAL={real}",
                "-o", out + ".tmp", src, "-lm"]
         subprocess.check_call(cmd)
         os.replace(out + ".tmp", out)

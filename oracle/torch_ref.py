@@ -86,3 +86,67 @@ def detector_loss(eps, sig, mu, E0, B0, nsteps: int, det_z: int):
         L = L + (E[:, det_z] ** 2).sum()
         f = step(f, eps, mu, sig)
     return L, f
+
+
+# ---------------------------------------------------------------- HV (Section III)
+EPS0_HV, MU0_HV = 3.0, 3.0  # lattice constants (vacuum speed 1/3)
+HVV = torch.tensor([[1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0], [0, 0, -1], [0, 0, 1]], dtype=torch.float64)
+
+
+def hv_fields(f, eps, mu, sig):
+    """E, B of HV state f [36][nz][ny][nx] (populations e_i then h_i, 3 components each)."""
+    e = f[:18].reshape(6, 3, *f.shape[1:])
+    h = f[18:].reshape(6, 3, *f.shape[1:])
+    D = e.sum(0)
+    B = h.sum(0)
+    return D / (EPS0_HV * eps), B
+
+
+def hv_equilibrium(D, B, eps, mu):
+    E = D / (EPS0_HV * eps)
+    H = B / (MU0_HV * mu)
+    v = HVV.reshape(6, 3, *([1] * (D.dim() - 1)))
+    vxH = torch.cross(v.expand(6, 3, *D.shape[1:]), H.expand(6, *H.shape), dim=1)
+    vxE = torch.cross(v.expand(6, 3, *D.shape[1:]), E.expand(6, *E.shape), dim=1)
+    feq_e = (D - 3 * vxH) / 6
+    feq_h = (B + 3 * vxE) / 6
+    return feq_e, feq_h
+
+
+def hv_step(f, eps, mu, sig):
+    """Modified HV collision (eq. CollisionmodifiedHV, tau = 1/2) and advection."""
+    e = f[:18].reshape(6, 3, *f.shape[1:])
+    h = f[18:].reshape(6, 3, *f.shape[1:])
+    D = e.sum(0)
+    B = h.sum(0)
+    E = D / (EPS0_HV * eps)
+    J = sig * E
+    feq_e, feq_h = hv_equilibrium(D, B, eps, mu)
+    v = HVV.reshape(6, 3, *([1] * (D.dim() - 1)))
+    Jv = (J.unsqueeze(0) * v).sum(1, keepdim=True)
+    T = -0.5 * Jv * v
+    ep = 2 * feq_e - e + T
+    hp = 2 * feq_h - h
+    out = []
+    for part in (ep, hp):
+        for i in range(6):
+            vx, vy, vz = (int(t) for t in HVV[i])
+            out.append(torch.roll(part[i], shifts=(vz, vy, vx), dims=(1, 2, 3)))
+    return torch.cat(out, dim=0)
+
+
+def hv_init(E0, B0, eps, mu):
+    D = EPS0_HV * eps * E0
+    feq_e, feq_h = hv_equilibrium(D, B0, eps, mu)
+    return torch.cat([feq_e.reshape(18, *E0.shape[1:]), feq_h.reshape(18, *E0.shape[1:])], dim=0)
+
+
+def hv_detector_loss(eps, sig, mu, E0, B0, nsteps: int, det_z: int):
+    """HV version of detector_loss."""
+    f = hv_init(E0, B0, eps, mu)
+    L = torch.zeros((), dtype=torch.float64)
+    for _ in range(nsteps):
+        E, _ = hv_fields(f, eps, mu, sig)
+        L = L + (E[:, det_z] ** 2).sum()
+        f = hv_step(f, eps, mu, sig)
+    return L, f

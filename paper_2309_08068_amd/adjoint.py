@@ -2,7 +2,7 @@
 hand-written adjoint (lbem_adjoint_forward / lbem_adjoint_backward).
 
 L(eps_r, sigma) = sum over the N collided states of sum_{x, y} |E(x, y, z_d)|^2
-for the MM lattice initialised to the equilibrium of (E0, B0).  The forward
+for an MM or HV lattice initialised to the equilibrium of (E0, B0).  The forward
 pass stores a checkpoint every K steps; backward recomputes each segment and
 runs the adjoint steps in reverse.  Gradients are FP64 on the device.
 """
@@ -25,6 +25,8 @@ class DetectorProblem:
     det_z: int
     K: int = 50
     mu_r: Optional[torch.Tensor] = None
+    model: str = "mm"
+    keep: int = 1          # trailing segments whose E frames the forward keeps
 
 
 class DetectorEnergy(torch.autograd.Function):
@@ -32,10 +34,10 @@ class DetectorEnergy(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, eps_r: torch.Tensor, sigma: torch.Tensor, prob: DetectorProblem):
-        lat = lbem.Lattice("mm", prob.shape, eps_r.detach(), prob.mu_r, sigma.detach(), device=eps_r.device)
+        lat = lbem.Lattice(prob.model, prob.shape, eps_r.detach(), prob.mu_r, sigma.detach(), device=eps_r.device)
         lat.set_fields(prob.E0, prob.B0)
-        ws = lat.adjoint_workspace(prob.nsteps, prob.K)
-        loss = lat.adjoint_forward(prob.nsteps, prob.K, prob.det_z, ws)
+        ws = lat.adjoint_workspace(prob.nsteps, prob.K, prob.keep)
+        loss = lat.adjoint_forward(prob.nsteps, prob.K, prob.det_z, ws, prob.keep)
         ctx.lat, ctx.ws, ctx.prob = lat, ws, prob
         ctx.dtypes = (eps_r.dtype, sigma.dtype)
         return loss.reshape(())

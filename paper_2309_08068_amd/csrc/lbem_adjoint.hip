@@ -1,8 +1,10 @@
 // lbem_adjoint.hip -- reverse-time (adjoint) differentiation of the
-// detector-plane loss with respect to the per-cell eps_r and sigma (MM model).
+// detector-plane loss with respect to the per-cell eps_r and sigma, for the MM
+// and the modified HV model.
 //
 // Forward, for fixed media theta = (eps_r, sigma):  f_{n+1} = S C_theta f_n,
-// with C(f) = 2 f_eq(m(f); theta) - f (Section II) and S the advection.
+// with C(f) = 2 f_eq(m(f); theta) - f (+ T for HV; Sections II-III) and S the
+// advection.
 // Loss L = sum_n l(f_n), l(f) = sum over the plane z_d of |E(f)|^2.
 // Adjoint:   mu_n = S^T lambda_{n+1},   lambda_n = C_theta^T mu_n + dl/df_n,
 //            lambda_{t0+N} = 0,
@@ -34,21 +36,28 @@ struct MMRev {
     __host__ __device__ static constexpr int opp(int q) { return MM::opp(q); }
 };
 
+// HV with every velocity reversed.
+struct HVRev {
+    static constexpr int Q = 36;
+    __host__ __device__ static constexpr int vel(int q, int a) { return -HV::vel(q, a); }
+    __host__ __device__ static constexpr int opp(int q) { return HV::opp(q); }
+};
+
 struct AdjArgs {
-    float *lam;  // adjoint state [50][N], FP32, AA layout of MMRev
+    float *lam;  // adjoint state [Q][N], FP32, AA layout of the reversed velocities
     const float *eps, *mu, *sig;
     const float *E;  // forward E(f_n) [3][N]
     uint32_t nx, ny, nz, N;
     int32_t det_z;
-    double *g_eps, *g_sig;  // [N] accumulators
-    const float *E0, *B0;   // initial fields (only on the last adjoint step), or null
+    float *g_eps, *g_sig;  // [N] FP32 accumulators of the current segment
+    const float *E0, *B0;  // initial fields (only on the last adjoint step), or null
 };
 
 // One adjoint step for one cell: mu (pre-collision adjoint, overwritten with
 // lambda), the forward field E of the same time level, the media; returns the
 // gradient contributions of this step.
 __device__ __forceinline__ void mm_adjoint_cell(float (&mu)[50], const float E[3], const CellMedia &m, bool plane,
-                                                const float *E0c, float &gE, float &gS) {
+                                                bool first, const float (&E0c)[3], float &gE, float &gS) {
     const float a = m.eps_r + 0.5f * m.sigma;
     const float ia = 1.0f / a;
     // adjoint moments of the moving populations
@@ -132,7 +141,7 @@ __device__ __forceinline__ void mm_adjoint_cell(float (&mu)[50], const float E[3
     }
     mu[48] = 2.f * Grho - mu[48];
     mu[49] = -mu[49];
-    if (E0c) {
+    if (first) {
         // f_0 = f_eq(E0, B0): d f_0^(0)_q / d eps_r = E0 . e_q / 4
         float Le0[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -148,81 +157,220 @@ __device__ __forceinline__ void mm_adjoint_cell(float (&mu)[50], const float E[3
     }
 }
 
-template <int ODD>
-__global__ __launch_bounds__(kBlock) void mm_adjoint_kernel(AdjArgs a) {
+
+// One HV adjoint step for one cell.  With D = sum e_i, B = sum h_i, E = D/eps,
+// H = B/mu, J = sigma E (eqs. MacroscopicFieldsHV, equilibriumHV,
+// CollisionmodifiedHV):  e'_i = D/3 - v_i x H - e_i - (J.v_i) v_i / 2,
+// h'_i = B/3 + v_i x E - h_i.  With S_e = sum mu_e_i, S_h = sum mu_h_i,
+// A = sum (mu_e_i . v_i) v_i, W = sum mu_h_i x v_i, Y = sum mu_e_i x v_i:
+//   (C^T mu)_e_j = S_e/3 - (sigma/eps) A/2 + W/eps - mu_e_j,
+//   (C^T mu)_h_j = S_h/3 - Y/mu - mu_h_j,
+// and the collision's dependence on theta through E and J gives
+//   dL/deps_r += (sigma/(2 eps_r)) E.A - E.W / eps_r,   dL/dsigma += -E.A/2.
+__device__ __forceinline__ void hv_adjoint_cell(float (&mu)[36], const float E[3], const CellMedia &m, bool plane,
+                                                bool first, const float (&E0c)[3], float &gE, float &gS) {
+    const float eps = kHVEps0 * m.eps_r, mmu = kHVMu0 * m.mu_r;
+    float Se[3] = {0.f, 0.f, 0.f}, Sh[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
+    float W[3] = {0.f, 0.f, 0.f}, Y[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const float ue[3] = {mu[3 * i], mu[3 * i + 1], mu[3 * i + 2]};
+        const float uh[3] = {mu[18 + 3 * i], mu[18 + 3 * i + 1], mu[18 + 3 * i + 2]};
+        const int v[3] = {kHVV[i][0], kHVV[i][1], kHVV[i][2]};
+        float uv = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Se[c] += ue[c];
+            Sh[c] += uh[c];
+            if (v[c] != 0) uv += v[c] > 0 ? ue[c] : -ue[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (v[c] != 0) A[c] += v[c] > 0 ? uv : -uv;
+            // (u x v)_c = u_{c+1} v_{c+2} - u_{c+2} v_{c+1}
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            W[c] += uh[c1] * float(v[c2]) - uh[c2] * float(v[c1]);
+            Y[c] += ue[c1] * float(v[c2]) - ue[c2] * float(v[c1]);
+        }
+    }
+    const float EA = E[0] * A[0] + E[1] * A[1] + E[2] * A[2];
+    const float EW = E[0] * W[0] + E[1] * W[1] + E[2] * W[2];
+    const float E2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
+    gE = (0.5f * m.sigma * EA - EW) / m.eps_r;
+    gS = -0.5f * EA;
+    if (plane) gE -= 2.f * E2 / m.eps_r;  // l = |E|^2, E = D / (eps0 eps_r)
+    float Ge[3], Gh[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Ge[c] = Se[c] * (1.f / 3.f) - 0.5f * (m.sigma / eps) * A[c] + W[c] / eps + (plane ? 2.f * E[c] / eps : 0.f);
+        Gh[c] = Sh[c] * (1.f / 3.f) - Y[c] / mmu;
+    }
+    float Le[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            mu[3 * i + c] = Ge[c] - mu[3 * i + c];
+            mu[18 + 3 * i + c] = Gh[c] - mu[18 + 3 * i + c];
+            Le[c] += mu[3 * i + c];
+        }
+    if (first) {
+        // e_i(0) = (eps E0 - 3 v_i x H0) / 6:  d e_i(0) / d eps_r = E0 / 2
+        gE += 0.5f * (E0c[0] * Le[0] + E0c[1] * Le[1] + E0c[2] * Le[2]);
+    }
+}
+
+template <class M>
+struct AdjCell;
+template <>
+struct AdjCell<MM> {
+    using Rev = MMRev;
+    __device__ static void step(float (&mu)[50], const float E[3], const CellMedia &m, bool plane, bool first,
+                                const float (&E0c)[3], float &gE, float &gS) {
+        mm_adjoint_cell(mu, E, m, plane, first, E0c, gE, gS);
+    }
+};
+template <>
+struct AdjCell<HV> {
+    using Rev = HVRev;
+    __device__ static void step(float (&mu)[36], const float E[3], const CellMedia &m, bool plane, bool first,
+                                const float (&E0c)[3], float &gE, float &gS) {
+        hv_adjoint_cell(mu, E, m, plane, first, E0c, gE, gS);
+    }
+};
+
+template <class M, int ODD>
+__global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjArgs a) {
     const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= a.N) return;
     const uint32_t nxy = a.nx * a.ny;
     const uint32_t z = c / nxy, rem = c - z * nxy, y = rem / a.nx, x = rem - y * a.nx;
     const Nbr nb = make_nbr(c, x, y, z, a.nx, a.ny, a.nz);
     const size_t N = a.N;
-    float mu[50];
-    gather<MMRev, ODD, StF32>(a.lam, N, nb, mu, 1.f);
+    using R = typename AdjCell<M>::Rev;
+    float mu[M::Q];
+    gather<R, ODD, StF32>(a.lam, N, nb, mu, 1.f);
     const float E[3] = {a.E[c], a.E[N + c], a.E[2 * N + c]};
     const CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
-    float E0c[3];
+    float E0c[3] = {0.f, 0.f, 0.f};
     if (a.E0) {
         E0c[0] = a.E0[c];
         E0c[1] = a.E0[N + c];
         E0c[2] = a.E0[2 * N + c];
     }
     float gE, gS;
-    mm_adjoint_cell(mu, E, m, int32_t(z) == a.det_z, a.E0 ? E0c : nullptr, gE, gS);
-    a.g_eps[c] += double(gE);
-    a.g_sig[c] += double(gS);
-    scatter<MMRev, ODD, StF32>(a.lam, N, nb, mu, 1.f);
+    AdjCell<M>::step(mu, E, m, int32_t(z) == a.det_z, a.E0 != nullptr, E0c, gE, gS);
+    a.g_eps[c] += gE;
+    a.g_sig[c] += gS;
+    Nbr nb2 = nb;
+    float *lam2 = a.lam;
+    late_addresses(nb2, lam2, mu[0]);
+    scatter<R, ODD, StF32>(lam2, N, nb2, mu, 1.f);
 }
 
-__global__ void scale_grads(double *g, double s, size_t n) {
+// Row form of the adjoint step (one block per x-row, see RowIO).
+template <class M, int ODD, int RB>
+__global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
+    using R = typename AdjCell<M>::Rev;
+    __shared__ float sh[ODD ? n_xshift<R>() : 1][RB];
+    const uint32_t row = blockIdx.x;
+    const uint32_t z = row / a.ny;
+    const uint32_t c = row * RB + threadIdx.x;
+    const size_t N = a.N;
+    RowIO<R, StF32, RB> io(a.lam, N, a.ny, a.nz, row);
+    float mu[M::Q];
+    io.template gather<ODD>(mu, sh, 1.f);
+    const float E[3] = {a.E[c], a.E[N + c], a.E[2 * N + c]};
+    const CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
+    float E0c[3] = {0.f, 0.f, 0.f};
+    if (a.E0) {
+        E0c[0] = a.E0[c];
+        E0c[1] = a.E0[N + c];
+        E0c[2] = a.E0[2 * N + c];
+    }
+    float gE, gS;
+    AdjCell<M>::step(mu, E, m, int32_t(z) == a.det_z, a.E0 != nullptr, E0c, gE, gS);
+    a.g_eps[c] += gE;
+    a.g_sig[c] += gS;
+    io.late(mu[0]);
+    io.template scatter<ODD>(mu, sh, 1.f);
+}
+
+// g64 += scale * g32 and g32 = 0 (end of a segment; FP64 across segments)
+__global__ void flush_grads(double *g64e, double *g64s, float *g32e, float *g32s, double scale, size_t n) {
     const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i < n) g[i] *= s;
+    if (i >= n) return;
+    g64e[i] += scale * double(g32e[i]);
+    g64s[i] += scale * double(g32s[i]);
+    g32e[i] = 0.f;
+    g32s[i] = 0.f;
 }
 
 struct AdjLayout {
-    size_t ckpt, frames, lam, total, state_bytes;
-    int64_t S;
+    size_t ckpt, frames, lam, g32, total, state_bytes;
+    int64_t S, keep;  // segments, and trailing segments whose frames the forward keeps
 };
 
-AdjLayout adj_layout(const lbem_desc *d, int64_t nsteps, int32_t K) {
+AdjLayout adj_layout(const lbem_desc *d, int64_t nsteps, int32_t K, int32_t keep) {
     AdjLayout L{};
     const size_t N = size_t(d->nx) * d->ny * d->nz;
     L.state_bytes = N * (d->model == LBEM_MM ? 50 : 36) * (d->storage == LBEM_F32 ? 4 : 2);
     L.S = (nsteps + K - 1) / K;
+    L.keep = std::max<int64_t>(1, std::min<int64_t>(keep, L.S));
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     size_t off = 0;
     L.ckpt = off;
     off = al(off + size_t(L.S + 1) * al(L.state_bytes));
     L.frames = off;
-    off = al(off + size_t(K) * 3 * N * 4);
+    off = al(off + size_t(L.keep) * size_t(K) * 3 * N * 4);
     L.lam = off;
-    off = al(off + N * 50 * 4);
+    off = al(off + N * (d->model == LBEM_MM ? 50 : 36) * 4);
+    L.g32 = off;
+    off = al(off + N * 2 * 4);
     L.total = off;
     return L;
 }
 
 uint32_t grid256(size_t n) { return uint32_t((n + kBlock - 1) / kBlock); }
 
+template <class M, int ODD>
+void launch_adjoint_p(const AdjArgs &aa, uint32_t rb, uint32_t rows, uint32_t g256, hipStream_t s) {
+    switch (rb) {
+        case 128: hipLaunchKernelGGL((adjoint_row_kernel<M, ODD, 128>), dim3(rows), dim3(128), 0, s, aa); break;
+        case 256: hipLaunchKernelGGL((adjoint_row_kernel<M, ODD, 256>), dim3(rows), dim3(256), 0, s, aa); break;
+        case 384: hipLaunchKernelGGL((adjoint_row_kernel<M, ODD, 384>), dim3(rows), dim3(384), 0, s, aa); break;
+        case 512: hipLaunchKernelGGL((adjoint_row_kernel<M, ODD, 512>), dim3(rows), dim3(512), 0, s, aa); break;
+        default: hipLaunchKernelGGL((adjoint_kernel<M, ODD>), dim3(g256), dim3(kBlock), 0, s, aa); break;
+    }
+}
+
+template <class M>
+void launch_adjoint(const AdjArgs &aa, int odd, uint32_t rb, uint32_t rows, uint32_t g256, hipStream_t s) {
+    if (odd) launch_adjoint_p<M, 1>(aa, rb, rows, g256, s);
+    else launch_adjoint_p<M, 0>(aa, rb, rows, g256, s);
+}
+
 }  // namespace
 
-lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, int32_t K, size_t *bytes) {
+lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, int32_t K, int32_t keep,
+                                        size_t *bytes) {
     size_t dummy;
     lbem_status st = lbem_workspace_size(desc, &dummy);
     if (st) return st;
     if (!bytes) return fail(LBEM_EINVAL, "bytes is NULL");
-    if (nsteps < 1 || K < 1) return fail(LBEM_EINVAL, "nsteps and K must be >= 1");
-    *bytes = adj_layout(desc, nsteps, K).total;
+    if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
+    *bytes = adj_layout(desc, nsteps, K, keep).total;
     return LBEM_OK;
 }
 
-lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t det_z, void *ws,
+lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z, void *ws,
                                  size_t ws_bytes, double *loss) {
     if (!lat || !ws || !loss) return fail(LBEM_EINVAL, "null argument");
-    if (nsteps < 1 || K < 1) return fail(LBEM_EINVAL, "nsteps and K must be >= 1");
-    if (lat->d.model != LBEM_MM) return fail(LBEM_ESTATE, "the adjoint is provided for the MM model");
+    if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
     if (lat->nsrc > 0 || lat->plane_z >= 0) return fail(LBEM_ESTATE, "the adjoint needs a lattice without sources");
     if (det_z < 0 || det_z >= lat->d.nz) return fail(LBEM_EINVAL, "detector plane z = %d outside the lattice", det_z);
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(LBEM_EINVAL, "workspace must be 256-byte aligned");
-    const AdjLayout L = adj_layout(&lat->d, nsteps, K);
+    const AdjLayout L = adj_layout(&lat->d, nsteps, K, keep);
     if (ws_bytes < L.total) return fail(LBEM_ENOMEM, "adjoint workspace has %zu bytes, needs %zu", ws_bytes, L.total);
     char *w = static_cast<char *>(ws);
     lbem_status st = lbem_set_detector(lat, det_z);
@@ -230,9 +378,15 @@ lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, i
     lat->adj_ws = nullptr;
     const int64_t t0 = lat->t;
     const size_t sb = (L.state_bytes + 255) & ~size_t(255);
+    float *frames = reinterpret_cast<float *>(w + L.frames);
     for (int64_t s = 0; s < L.S; ++s) {
+        const int64_t ks = std::min<int64_t>(K, nsteps - s * K);
         st = lbem_save_state(lat, w + L.ckpt + size_t(s) * sb);
-        if (!st) st = lbem_step(lat, std::min<int64_t>(K, nsteps - s * K));
+        if (st) return st;
+        // the last `keep` segments also keep E(f_n) of each step, so the
+        // reverse pass does not recompute them
+        const int64_t slot = s - (L.S - L.keep);
+        st = step_impl(lat, ks, slot >= 0 ? frames + size_t(slot) * K * 3 * lat->N : nullptr);
         if (st) return st;
     }
     st = lbem_save_state(lat, w + L.ckpt + size_t(L.S) * sb);
@@ -242,6 +396,7 @@ lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, i
     lat->adj_t0 = t0;
     lat->adj_nsteps = nsteps;
     lat->adj_K = K;
+    lat->adj_keep = int32_t(L.keep);
     lat->adj_det = det_z;
     return LBEM_OK;
 }
@@ -253,7 +408,7 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
     if ((E0 == nullptr) != (B0 == nullptr)) return fail(LBEM_EINVAL, "give both E0 and B0 or neither");
     const int64_t nsteps = lat->adj_nsteps, t0 = lat->adj_t0;
     const int32_t K = lat->adj_K;
-    const AdjLayout L = adj_layout(&lat->d, nsteps, K);
+    const AdjLayout L = adj_layout(&lat->d, nsteps, K, lat->adj_keep);
     if (ws_bytes < L.total) return fail(LBEM_ENOMEM, "adjoint workspace too small");
     char *w = static_cast<char *>(ws);
     const size_t sb = (L.state_bytes + 255) & ~size_t(255);
@@ -262,7 +417,9 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
     // gradients and the adjoint state start at zero
     hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(grad_eps), 2 * N);
     hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(grad_sigma), 2 * N);
-    hipLaunchKernelGGL(zero_bytes, dim3(grid256(50 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.lam), 50 * N);
+    hipLaunchKernelGGL(zero_bytes, dim3(grid256(lat->Q * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.lam),
+                       lat->Q * N);
+    hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.g32), 2 * N);
     lbem_status st = hip_check(hipGetLastError(), "zero");
     if (st) return st;
     float *frames = reinterpret_cast<float *>(w + L.frames);
@@ -276,39 +433,43 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
     aa.nz = lat->d.nz;
     aa.N = lat->N;
     aa.det_z = lat->adj_det;
-    aa.g_eps = grad_eps;
-    aa.g_sig = grad_sigma;
+    aa.g_eps = reinterpret_cast<float *>(w + L.g32);
+    aa.g_sig = aa.g_eps + N;
+    const uint32_t rb = row_block(&lat->d);
     int64_t j = 0;  // adjoint steps done (parity of the adjoint AA layout)
     for (int64_t seg = L.S - 1; seg >= 0; --seg) {
         const int64_t tseg = t0 + seg * K;
         const int64_t ks = std::min<int64_t>(K, nsteps - seg * K);
-        st = lbem_load_state(lat, w + L.ckpt + size_t(seg) * sb, tseg);
-        if (st) return st;
-        // recompute the segment, keeping E(f_n) of every step
-        StepArgs a = base_step_args(lat);
-        for (int64_t k = 0; k < ks; ++k) {
-            a.E_out = frames + size_t(k) * 3 * N;
-            dispatch_step(lat, a, int(lat->t & 1));
-            st = hip_check(hipGetLastError(), "recompute launch");
+        const int64_t slot = seg - (L.S - L.keep);
+        float *segf = frames + size_t(slot >= 0 ? slot : 0) * K * 3 * N;
+        if (slot < 0) {
+            // recompute the segment, keeping E(f_n) of every step
+            st = lbem_load_state(lat, w + L.ckpt + size_t(seg) * sb, tseg);
             if (st) return st;
-            lat->t += 1;
+            StepArgs a = base_step_args(lat);
+            for (int64_t k = 0; k < ks; ++k) {
+                a.E_out = segf + size_t(k) * 3 * N;
+                dispatch_step(lat, a, int(lat->t & 1));
+                st = hip_check(hipGetLastError(), "recompute launch");
+                if (st) return st;
+                lat->t += 1;
+            }
         }
         // adjoint steps of the segment, last time level first
         for (int64_t k = ks - 1; k >= 0; --k) {
-            aa.E = frames + size_t(k) * 3 * N;
+            aa.E = segf + size_t(k) * 3 * N;
             const bool first = seg == 0 && k == 0;
             aa.E0 = first ? E0 : nullptr;
             aa.B0 = first ? B0 : nullptr;
-            if (j & 1) hipLaunchKernelGGL(mm_adjoint_kernel<1>, dim3(grid256(N)), dim3(kBlock), 0, s, aa);
-            else hipLaunchKernelGGL(mm_adjoint_kernel<0>, dim3(grid256(N)), dim3(kBlock), 0, s, aa);
+            const int odd = int(j & 1);
+            if (lat->d.model == LBEM_MM) launch_adjoint<MM>(aa, odd, rb, lat->nblocks, grid256(N), s);
+            else launch_adjoint<HV>(aa, odd, rb, lat->nblocks, grid256(N), s);
             st = hip_check(hipGetLastError(), "adjoint launch");
             if (st) return st;
             ++j;
         }
-    }
-    if (scale != 1.0) {
-        hipLaunchKernelGGL(scale_grads, dim3(grid256(N)), dim3(kBlock), 0, s, grad_eps, scale, N);
-        hipLaunchKernelGGL(scale_grads, dim3(grid256(N)), dim3(kBlock), 0, s, grad_sigma, scale, N);
+        hipLaunchKernelGGL(flush_grads, dim3(grid256(N)), dim3(kBlock), 0, s, grad_eps, grad_sigma, aa.g_eps, aa.g_sig,
+                           scale, N);
     }
     // leave the lattice as the forward left it
     st = lbem_load_state(lat, w + L.ckpt + size_t(L.S) * sb, t0 + nsteps);

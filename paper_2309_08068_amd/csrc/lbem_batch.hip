@@ -62,11 +62,15 @@ __device__ __forceinline__ void cell_1d(typename ST::T *__restrict__ pop, size_t
         *out = o;
         return;
     }
+    // store addresses formed after the collision (see late_addresses)
+    uint32_t g2 = g, gm2 = gm, gp2 = gp;
+    typename ST::T *pop2 = pop;
+    asm volatile("" : "+v"(g2), "+v"(gm2), "+v"(gp2), "+s"(pop2) : "v"(f[0]));
 #pragma unroll
     for (int q = 0; q < M::Q; ++q) {
         const int vz = M::vel(q, 2);
-        if (ODD) ST::store(pop + size_t(q) * total, vz > 0 ? gp : (vz < 0 ? gm : g), f[q], 1.f);
-        else ST::store(pop + size_t(M::opp(q)) * total, g, f[q], 1.f);
+        if (ODD) ST::store(pop2 + size_t(q) * total, vz > 0 ? gp2 : (vz < 0 ? gm2 : g2), f[q], 1.f);
+        else ST::store(pop2 + size_t(M::opp(q)) * total, g2, f[q], 1.f);
     }
 }
 

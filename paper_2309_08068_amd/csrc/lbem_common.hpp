@@ -133,6 +133,105 @@ __device__ __forceinline__ void scatter(typename ST::T *__restrict__ pop, size_t
     }
 }
 
+// In-place streaming stores population q where it loaded opp(q), so a
+// compiler left alone keeps every load address live until the matching store
+// and runs out of registers.  Passing the neighbour table and the base pointer
+// through an empty asm statement that also consumes a collision result makes
+// them opaque: the store addresses are then formed after the collision.
+template <class P>
+__device__ __forceinline__ void late_addresses(Nbr &nb, P *&base, float after) {
+    asm volatile(""
+                 : "+v"(nb.c), "+v"(nb.xs[0]), "+v"(nb.xs[1]), "+v"(nb.xs[2]), "+v"(nb.ys[0]), "+v"(nb.ys[1]),
+                   "+v"(nb.ys[2]), "+v"(nb.zs[0]), "+v"(nb.zs[1]), "+v"(nb.zs[2]), "+s"(base)
+                 : "v"(after));
+}
+
+// ------------------------------------------------------------ row form
+// Number of populations of M whose velocity has a non-zero x component.
+template <class M>
+constexpr int n_xshift() {
+    int n = 0;
+    for (int q = 0; q < M::Q; ++q) n += M::vel(q, 0) != 0;
+    return n;
+}
+
+// Gather / scatter of the in-place AA streaming for a block that owns one
+// whole x-row of RB cells (y, z uniform).  Every HBM access is the aligned
+// row segment of one population plane, with the non-temporal hint; the +-1 x
+// shifts of the odd parity go through the LDS array sh[n_xshift][RB], which
+// keeps partial cache lines out of the memory traffic.  Addresses are a
+// uniform row base (scalar registers) plus one 32-bit byte offset of x (a
+// plane of a lattice in this form holds fewer than 2^30 cells).
+template <class M, class ST, int RB>
+struct RowIO {
+    using T = typename ST::T;
+    const char *pop;
+    size_t N;
+    uint32_t ny, x, xo;
+    uint32_t yr[3], zr[3];
+
+    __device__ RowIO(const void *p, size_t n, uint32_t ny_, uint32_t nz, uint32_t row)
+        : pop(static_cast<const char *>(p)), N(n), ny(ny_), x(threadIdx.x), xo(threadIdx.x * uint32_t(sizeof(T))) {
+        const uint32_t y = row % ny_, z = row / ny_;
+        yr[0] = y == 0 ? ny_ - 1 : y - 1;
+        yr[1] = y;
+        yr[2] = y + 1 == ny_ ? 0 : y + 1;
+        zr[0] = z == 0 ? nz - 1 : z - 1;
+        zr[1] = z;
+        zr[2] = z + 1 == nz ? 0 : z + 1;
+    }
+    __device__ T *at(int q, int dy, int dz) const {
+        return reinterpret_cast<T *>(const_cast<char *>(pop) +
+                                     (size_t(q) * N + size_t(yr[dy + 1] + ny * zr[dz + 1]) * RB) * sizeof(T) + xo);
+    }
+    // store addresses formed after the collision (see late_addresses)
+    __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo) : "v"(after)); }
+
+    template <int ODD>
+    __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale) const {
+        if (!ODD) {
+#pragma unroll
+            for (int q = 0; q < M::Q; ++q) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
+        } else {
+            // f_q(x) = slot (opp q, x - v_q): aligned source row, x shift in LDS
+            int k = 0;
+#pragma unroll
+            for (int q = 0; q < M::Q; ++q) {
+                const T v = raw<T, true>(at(M::opp(q), -M::vel(q, 1), -M::vel(q, 2)));
+                if (M::vel(q, 0) == 0) f[q] = ST::cvt(v, inv_scale);
+                else sh[k++][x] = v;
+            }
+            __syncthreads();
+            k = 0;
+#pragma unroll
+            for (int q = 0; q < M::Q; ++q)
+                if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][(x + RB - M::vel(q, 0)) % RB], inv_scale);
+            __syncthreads();
+        }
+    }
+
+    template <int ODD>
+    __device__ void scatter(const float (&f)[M::Q], T (*sh)[RB], float scale) const {
+        if (!ODD) {
+#pragma unroll
+            for (int q = 0; q < M::Q; ++q) put<T, true>(at(M::opp(q), 0, 0), ST::pack(f[q], scale));
+        } else {
+            // f'_q(x) goes to slot (q, x + v_q): x shift in LDS, aligned stores
+            int k = 0;
+#pragma unroll
+            for (int q = 0; q < M::Q; ++q) {
+                if (M::vel(q, 0) == 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
+                else sh[k++][(x + M::vel(q, 0) + RB) % RB] = ST::pack(f[q], scale);
+            }
+            __syncthreads();
+            k = 0;
+#pragma unroll
+            for (int q = 0; q < M::Q; ++q)
+                if (M::vel(q, 0) != 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), sh[k++][x]);
+        }
+    }
+};
+
 // ------------------------------------------------------------ reductions
 // Sum of one double per thread over a block of kBlock threads, in a fixed
 // order (wavefront butterfly, then the NW wave partials in order).  The

@@ -89,10 +89,14 @@ struct lbem_lattice {
     int64_t en_cap, en_t0;
     double *en_series;
     int64_t t;
+    // launch tuning of the step kernel per parity: address form, blocks per CU
+    // cap, and the dynamic LDS that implements the cap
+    int32_t tune_form[2], tune_cap[2];
+    size_t tune_pad[2];
     // adjoint session (lbem_adjoint_forward)
     void *adj_ws;
     int64_t adj_t0, adj_nsteps;
-    int32_t adj_K, adj_det;
+    int32_t adj_K, adj_keep, adj_det;
 };
 
 
@@ -102,4 +106,7 @@ namespace lbem {
 StepArgs base_step_args(lbem_lattice *lat);
 // Launch one step kernel of the lattice's model and storage.
 void dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd);
+// lbem_step with every observation; if frames is set, E of the state collided
+// by step s is also written to frames + s * 3 N.
+lbem_status step_impl(lbem_lattice *lat, int64_t nsteps, float *frames);
 }  // namespace lbem

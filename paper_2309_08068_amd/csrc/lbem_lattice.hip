@@ -57,7 +57,13 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     CellFields o;
     Cell<M>::collide(f, m, Js, o);
     if (int32_t(z) == a.plane_z) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
-    if (live) scatter<M, ODD, ST>(pop, N, nb, f, a.scale);
+    if (live) {
+        // store addresses formed after the collision (see late_addresses)
+        Nbr nb2 = nb;
+        auto *pop2 = pop;
+        late_addresses(nb2, pop2, f[0]);
+        scatter<M, ODD, ST>(pop2, N, nb2, f, a.scale);
+    }
 
     // ---- observation of the state this step collided
     if (a.E_out && live) {
@@ -90,56 +96,26 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     }
 }
 
-// Number of populations of M whose velocity has a non-zero x component.
-template <class M>
-constexpr int n_xshift() {
-    int n = 0;
-    for (int q = 0; q < M::Q; ++q) n += M::vel(q, 0) != 0;
-    return n;
-}
-
 // Row form of the step for lattices whose x extent equals the block (RB
-// threads = one full x-row; y and z are uniform per block).  Every HBM access
-// is a whole, aligned row segment with the non-temporal hint; the +-1 x shifts
-// of the odd parity go through LDS, which keeps partial cache lines out of the
-// memory traffic.  Same arithmetic as step_kernel, bit for bit.
-template <class M, int ODD, class ST, int RB>
+// threads = one full x-row; y and z are uniform per block), see RowIO.  Same
+// arithmetic as step_kernel, bit for bit.
+// LATE = 1 forms the store addresses after the collision (see late_addresses);
+// which form is faster depends on model, storage and parity, so both exist
+// and the launch tuning picks one.
+template <class M, int ODD, class ST, int RB, int LATE>
 __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
-    constexpr int NS = ODD ? n_xshift<M>() : 1;
     constexpr int NW = RB / 64;
     using T = typename ST::T;
-    __shared__ T sh[NS][RB];
+    __shared__ T sh[ODD ? n_xshift<M>() : 1][RB];
     __shared__ double sm_en[NW], sm_det[NW];
     const uint32_t row = blockIdx.x;  // y + ny z
     const uint32_t x = threadIdx.x;
-    const uint32_t y = row % a.ny, z = row / a.ny;
+    const uint32_t z = row / a.ny;
     const uint32_t c = row * RB + x;
     const size_t N = a.N;
-    T *pop = static_cast<T *>(a.pop);
-    const uint32_t yr[3] = {y == 0 ? a.ny - 1 : y - 1, y, y + 1 == a.ny ? 0 : y + 1};
-    const uint32_t zr[3] = {z == 0 ? a.nz - 1 : z - 1, z, z + 1 == a.nz ? 0 : z + 1};
-    auto rowoff = [&](int dy, int dz) -> uint32_t { return (yr[dy + 1] + a.ny * zr[dz + 1]) * RB; };
-
+    RowIO<M, ST, RB> io(a.pop, N, a.ny, a.nz, row);
     float f[M::Q];
-    if (!ODD) {
-#pragma unroll
-        for (int q = 0; q < M::Q; ++q) f[q] = ST::template load<true>(pop + size_t(q) * N, c, a.inv_scale);
-    } else {
-        // f_q(x) = slot (opp q, x - v_q): load the aligned source row, shift x in LDS
-        int k = 0;
-#pragma unroll
-        for (int q = 0; q < M::Q; ++q) {
-            const T *src = pop + size_t(M::opp(q)) * N + rowoff(-M::vel(q, 1), -M::vel(q, 2));
-            if (M::vel(q, 0) == 0) f[q] = ST::template load<true>(src, x, a.inv_scale);
-            else sh[k++][x] = raw<T, true>(src + x);
-        }
-        __syncthreads();
-        k = 0;
-#pragma unroll
-        for (int q = 0; q < M::Q; ++q)
-            if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][(x + RB - M::vel(q, 0)) % RB], a.inv_scale);
-        __syncthreads();
-    }
+    io.template gather<ODD>(f, sh, a.inv_scale);
 
     CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
     float Js[3] = {0.f, 0.f, 0.f};
@@ -156,27 +132,8 @@ __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
     Cell<M>::collide(f, m, Js, o);
     if (int32_t(z) == a.plane_z) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
 
-    if (!ODD) {
-#pragma unroll
-        for (int q = 0; q < M::Q; ++q) ST::template store<true>(pop + size_t(M::opp(q)) * N, c, f[q], a.scale);
-    } else {
-        // f'_q(x) goes to slot (q, x + v_q): shift x in LDS, store aligned rows
-        int k = 0;
-#pragma unroll
-        for (int q = 0; q < M::Q; ++q) {
-            T *dst = pop + size_t(q) * N + rowoff(M::vel(q, 1), M::vel(q, 2));
-            if (M::vel(q, 0) == 0) ST::template store<true>(dst, x, f[q], a.scale);
-            else sh[k++][(x + M::vel(q, 0) + RB) % RB] = ST::pack(f[q], a.scale);
-        }
-        __syncthreads();
-        k = 0;
-#pragma unroll
-        for (int q = 0; q < M::Q; ++q)
-            if (M::vel(q, 0) != 0) {
-                T *dst = pop + size_t(q) * N + rowoff(M::vel(q, 1), M::vel(q, 2));
-                put<T, true>(dst + x, sh[k++][x]);
-            }
-    }
+    if (LATE) io.late(f[0]);
+    io.template scatter<ODD>(f, sh, a.scale);
 
     // ---- observation of the state this step collided
     if (a.E_out) {
@@ -415,6 +372,12 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     lat->plane_z = -1;
     lat->det_z = -1;
     lat->t = 0;
+    // default launch tuning (measured on MI355X at 256^3): late store addresses
+    // on the odd parity except for MM with FP32 storage, no occupancy cap
+    lat->tune_form[0] = 0;
+    lat->tune_form[1] = (desc->model == LBEM_MM && desc->storage == LBEM_F32) ? 0 : 1;
+    lat->tune_cap[0] = lat->tune_cap[1] = 0;
+    lat->tune_pad[0] = lat->tune_pad[1] = 0;
     hipStream_t s = lat->stream;
     float *eps = reinterpret_cast<float *>(lat->ws + L.eps);
     float *mu = reinterpret_cast<float *>(lat->ws + L.mu);
@@ -627,34 +590,60 @@ lbem_status lbem_set_energy_series(lbem_lattice *lat, int32_t every, int64_t cap
     return LBEM_OK;
 }
 
+// Kernel of the row form for a tuning choice (form = LATE) and its static LDS.
+template <class M, int ODD, class ST, int RB>
+static const void *row_kernel_ptr(int form) {
+    return form ? reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1>)
+                : reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 0>);
+}
+
 template <class M, int ODD, class ST>
-static void launch_step(const StepArgs &a, uint32_t nblocks, uint32_t rb, hipStream_t s) {
+static const void *step_kernel_ptr(uint32_t rb, int form) {
     switch (rb) {
-        case 128: hipLaunchKernelGGL((row_step_kernel<M, ODD, ST, 128>), dim3(nblocks), dim3(128), 0, s, a); break;
-        case 256: hipLaunchKernelGGL((row_step_kernel<M, ODD, ST, 256>), dim3(nblocks), dim3(256), 0, s, a); break;
-        case 384: hipLaunchKernelGGL((row_step_kernel<M, ODD, ST, 384>), dim3(nblocks), dim3(384), 0, s, a); break;
-        case 512: hipLaunchKernelGGL((row_step_kernel<M, ODD, ST, 512>), dim3(nblocks), dim3(512), 0, s, a); break;
-        default: hipLaunchKernelGGL((step_kernel<M, ODD, ST>), dim3(nblocks), dim3(kBlock), 0, s, a); break;
+        case 128: return row_kernel_ptr<M, ODD, ST, 128>(form);
+        case 256: return row_kernel_ptr<M, ODD, ST, 256>(form);
+        case 384: return row_kernel_ptr<M, ODD, ST, 384>(form);
+        case 512: return row_kernel_ptr<M, ODD, ST, 512>(form);
+        default: return reinterpret_cast<const void *>(&step_kernel<M, ODD, ST>);
     }
 }
 
 template <class M, int ODD>
-static void dispatch_step_storage(const lbem_lattice *lat, const StepArgs &a) {
+static const void *step_kernel_ptr_st(const lbem_lattice *lat, int form) {
+    const uint32_t rb = row_block(&lat->d);
     switch (lat->d.storage) {
-        case LBEM_F32: launch_step<M, ODD, StF32>(a, lat->nblocks, row_block(&lat->d), lat->stream); break;
-        case LBEM_BF16: launch_step<M, ODD, StBF16>(a, lat->nblocks, row_block(&lat->d), lat->stream); break;
-        default: launch_step<M, ODD, StF16>(a, lat->nblocks, row_block(&lat->d), lat->stream); break;
+        case LBEM_F32: return step_kernel_ptr<M, ODD, StF32>(rb, form);
+        case LBEM_BF16: return step_kernel_ptr<M, ODD, StBF16>(rb, form);
+        default: return step_kernel_ptr<M, ODD, StF16>(rb, form);
     }
 }
 
+static const void *step_kernel_of(const lbem_lattice *lat, int odd, int form) {
+    if (lat->d.model == LBEM_MM) return odd ? step_kernel_ptr_st<MM, 1>(lat, form) : step_kernel_ptr_st<MM, 0>(lat, form);
+    return odd ? step_kernel_ptr_st<HV, 1>(lat, form) : step_kernel_ptr_st<HV, 0>(lat, form);
+}
+
+// Dynamic LDS that caps the resident blocks per compute unit at `cap`
+// (0: no cap), given the kernel's static LDS.
+static size_t lds_pad_for(const void *kernel, int cap) {
+    if (cap <= 0) return 0;
+    hipFuncAttributes attr{};
+    if (hipFuncGetAttributes(&attr, kernel) != hipSuccess) return 0;
+    int dev = 0, lds_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        lds_cu <= 0)
+        return 0;
+    const size_t per_block = size_t(lds_cu) / size_t(cap + 1) + 1;  // cap blocks fit, cap + 1 do not
+    const size_t need = per_block > attr.sharedSizeBytes ? per_block - attr.sharedSizeBytes : 0;
+    return std::min<size_t>(need, 65536 - attr.sharedSizeBytes);
+}
+
 void lbem::dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd) {
-    if (lat->d.model == LBEM_MM) {
-        if (odd) dispatch_step_storage<MM, 1>(lat, a);
-        else dispatch_step_storage<MM, 0>(lat, a);
-    } else {
-        if (odd) dispatch_step_storage<HV, 1>(lat, a);
-        else dispatch_step_storage<HV, 0>(lat, a);
-    }
+    const void *k = step_kernel_of(lat, odd, lat->tune_form[odd]);
+    const uint32_t rb = row_block(&lat->d);
+    void *args[] = {const_cast<StepArgs *>(&a)};
+    (void)hipLaunchKernel(k, dim3(lat->nblocks), dim3(rb ? rb : kBlock), args, lat->tune_pad[odd], lat->stream);
 }
 
 namespace lbem {
@@ -691,6 +680,10 @@ StepArgs lbem::base_step_args(lbem_lattice *lat) {
 lbem_status lbem_step(lbem_lattice *lat, int64_t nsteps) {
     if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
     if (nsteps < 0) return fail(LBEM_EINVAL, "nsteps < 0");
+    return step_impl(lat, nsteps, nullptr);
+}
+
+lbem_status lbem::step_impl(lbem_lattice *lat, int64_t nsteps, float *frames) {
     const WsLayout &L = lat->L;
     StepArgs a = base_step_args(lat);
     if (lat->nprobe > 0) {
@@ -718,6 +711,7 @@ lbem_status lbem_step(lbem_lattice *lat, int64_t nsteps) {
         if (lat->nprobe > 0) a.prb_row = lat->prb_series + ((t - lat->prb_t0) % lat->prb_cap) * lat->nprobe * 6;
         const bool en = lat->en_every > 0 && (t - lat->en_t0) % lat->en_every == 0;
         a.en_part = en ? en_part : nullptr;
+        a.E_out = frames ? frames + size_t(s) * 3 * lat->N : nullptr;
         dispatch_step(lat, a, int(t & 1));
         if (en) {
             double *dst = lat->en_series + ((t - lat->en_t0) / lat->en_every) % lat->en_cap;
@@ -813,4 +807,80 @@ lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t) {
     if (st) return st;
     lat->t = t;
     return LBEM_OK;
+}
+
+lbem_status lbem_set_tuning(lbem_lattice *lat, const int32_t *form, const int32_t *blocks_per_cu) {
+    if (!lat || !form || !blocks_per_cu) return fail(LBEM_EINVAL, "null argument");
+    for (int p = 0; p < 2; ++p) {
+        if (form[p] != 0 && form[p] != 1) return fail(LBEM_EINVAL, "form must be 0 or 1");
+        if (blocks_per_cu[p] < 0 || blocks_per_cu[p] > 64) return fail(LBEM_EINVAL, "blocks_per_cu must be in [0, 64]");
+    }
+    for (int p = 0; p < 2; ++p) {
+        lat->tune_form[p] = form[p];
+        lat->tune_cap[p] = blocks_per_cu[p];
+        lat->tune_pad[p] = lds_pad_for(step_kernel_of(lat, p, form[p]), blocks_per_cu[p]);
+    }
+    return LBEM_OK;
+}
+
+lbem_status lbem_get_tuning(lbem_lattice *lat, int32_t *form, int32_t *blocks_per_cu) {
+    if (!lat || !form || !blocks_per_cu) return fail(LBEM_EINVAL, "null argument");
+    for (int p = 0; p < 2; ++p) {
+        form[p] = lat->tune_form[p];
+        blocks_per_cu[p] = lat->tune_cap[p];
+    }
+    return LBEM_OK;
+}
+
+lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup) {
+    if (!lat || !backup) return fail(LBEM_EINVAL, "null argument");
+    if (trial_steps < 1) return fail(LBEM_EINVAL, "trial_steps must be >= 1");
+    const size_t bytes = size_t(lat->N) * lat->Q * lat->sbytes;
+    lbem_status st =
+        hip_check(hipMemcpyAsync(backup, lat->ws + lat->L.pop, bytes, hipMemcpyDeviceToDevice, lat->stream), "backup");
+    if (st) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    st = hip_check(hipEventCreate(&e0), "event");
+    if (!st) st = hip_check(hipEventCreate(&e1), "event");
+    static const int caps[] = {0, 2, 3, 4};
+    int32_t best_form[2] = {lat->tune_form[0], lat->tune_form[1]};
+    int32_t best_cap[2] = {lat->tune_cap[0], lat->tune_cap[1]};
+    // every candidate times one parity's kernel alone; the data it leaves is
+    // not a valid state, which is why the state is restored afterwards
+    const StepArgs a = base_step_args(lat);
+    for (int p = 0; p < 2 && !st; ++p) {
+        float best = 1e30f;
+        for (int form = 0; form < 2 && !st; ++form)
+            for (int cap : caps) {
+                int32_t f2[2] = {lat->tune_form[0], lat->tune_form[1]}, c2[2] = {lat->tune_cap[0], lat->tune_cap[1]};
+                f2[p] = form;
+                c2[p] = cap;
+                st = lbem_set_tuning(lat, f2, c2);
+                if (st) break;
+                dispatch_step(lat, a, p);  // warm-up
+                st = hip_check(hipEventRecord(e0, lat->stream), "record");
+                for (int k = 0; k < trial_steps && !st; ++k) dispatch_step(lat, a, p);
+                if (!st) st = hip_check(hipGetLastError(), "trial launch");
+                if (!st) st = hip_check(hipEventRecord(e1, lat->stream), "record");
+                if (!st) st = hip_check(hipEventSynchronize(e1), "sync");
+                float ms = 0.f;
+                if (!st) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+                if (!st && ms < best) {
+                    best = ms;
+                    best_form[p] = form;
+                    best_cap[p] = cap;
+                }
+            }
+        if (!st) {
+            int32_t f2[2] = {lat->tune_form[0], lat->tune_form[1]}, c2[2] = {lat->tune_cap[0], lat->tune_cap[1]};
+            f2[p] = best_form[p];
+            c2[p] = best_cap[p];
+            st = lbem_set_tuning(lat, f2, c2);
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    lbem_status st2 =
+        hip_check(hipMemcpyAsync(lat->ws + lat->L.pop, backup, bytes, hipMemcpyDeviceToDevice, lat->stream), "restore");
+    return st ? st : st2;
 }

@@ -246,17 +246,23 @@ def smooth_field(shape2: Tuple[int, int, int], sigma_f: float, seed: int) -> np.
 
 def slab(model: str = "mm", shape=(128, 128, 256), slab_z=(96, 160), eps_range=(1.0, 4.0),
          sigma_range=(0.0, 0.02), pulse_z: float = 56.0, pulse_width: float = 10.0, det_z: int = 230,
-         sponge: int = 16, sigma_max: Optional[float] = None, steps: int = 1500, seed: int = 0) -> Workload:
-    """Inverse-design lattice: smooth random eps_r and sigma inside a slab,
-    fixed sigma sponges at both z ends, plane-wave pulse, detector plane."""
+         sponge: int = 16, sigma_max: Optional[float] = None, steps: int = 1500, seed: int = 0,
+         smooth: float = 4.0) -> Workload:
+    """Inverse-design lattice: smooth random eps_r and sigma inside a slab
+    (tapered to the background by a sin^2 window along z), fixed sigma sponges
+    at both z ends, plane-wave pulse, detector plane."""
     nx, ny, nz = shape
     z0, z1 = slab_z
     eps = np.ones((nz, ny, nx))
     sg = np.zeros((nz, ny, nx))
-    u1 = smooth_field((z1 - z0, ny, nx), 4.0, seed)
-    u2 = smooth_field((z1 - z0, ny, nx), 4.0, seed + 1)
-    eps[z0:z1] = eps_range[0] + (eps_range[1] - eps_range[0]) * u1
-    sg[z0:z1] = sigma_range[0] + (sigma_range[1] - sigma_range[0]) * u2
+    u1 = smooth_field((z1 - z0, ny, nx), smooth, seed)
+    u2 = smooth_field((z1 - z0, ny, nx), smooth, seed + 1)
+    # taper the random fields to the background at the slab faces: a sharp
+    # face with eps varying along it grows an unstable mode in both models
+    zz = np.arange(z1 - z0, dtype=np.float64)
+    win = (np.sin(np.pi * (zz + 0.5) / (z1 - z0)) ** 2)[:, None, None]
+    eps[z0:z1] = eps_range[0] + (eps_range[1] - eps_range[0]) * u1 * win
+    sg[z0:z1] = sigma_range[0] + (sigma_range[1] - sigma_range[0]) * u2 * win
     smax = SPONGE_SIGMA_MAX[model] if sigma_max is None else sigma_max
     sz = sponge_profile(nz, sponge, smax)
     sg = np.maximum(sg, sz[:, None, None])

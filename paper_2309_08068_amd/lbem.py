@@ -44,9 +44,12 @@ SIGNATURES = {
     "lbem_get_fields": (_I32, [_P, _P, _P, _P, _P]),
     "lbem_energy": (_I32, [_P, _P]),
     "lbem_save_state": (_I32, [_P, _P]),
+    "lbem_set_tuning": (_I32, [_P, _P, _P]),
+    "lbem_get_tuning": (_I32, [_P, _P, _P]),
+    "lbem_autotune": (_I32, [_P, _I32, _P]),
     "lbem_load_state": (_I32, [_P, _P, _I64]),
-    "lbem_adjoint_workspace_size": (_I32, [_P, _I64, _I32, C.POINTER(_SZ)]),
-    "lbem_adjoint_forward": (_I32, [_P, _I64, _I32, _I32, _P, _SZ, _P]),
+    "lbem_adjoint_workspace_size": (_I32, [_P, _I64, _I32, _I32, C.POINTER(_SZ)]),
+    "lbem_adjoint_forward": (_I32, [_P, _I64, _I32, _I32, _I32, _P, _SZ, _P]),
     "lbem_adjoint_backward": (_I32, [_P, _P, _SZ, _P, _P, _D, _P, _P]),
     "lbem_batch_workspace_size": (_I32, [_I32, _I32, _I32, _P, C.POINTER(_SZ)]),
     "lbem_batch_create": (_I32, [_I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P, C.POINTER(_P)]),
@@ -77,8 +80,10 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load liblbem.so and declare its signatures (no GPU needed to load)."""
+    """Load liblbem.so and declare its signatures (no GPU needed to load).
+    The environment variable LBEM_LIBRARY names another build to load instead."""
     global _lib
+    path = os.environ.get("LBEM_LIBRARY", path)
     if _lib is None:
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
@@ -256,16 +261,40 @@ class Lattice:
             raise ValueError("state buffer too small")
         check(self.lib.lbem_load_state(self.h, _ptr(src), int(t)))
 
-    # ------------------------------------------------------------ adjoint
-    def adjoint_workspace(self, nsteps: int, K: int) -> torch.Tensor:
-        size = C.c_size_t()
-        check(self.lib.lbem_adjoint_workspace_size(C.byref(self._desc), int(nsteps), int(K), C.byref(size)))
-        return torch.empty(size.value, dtype=torch.uint8, device=self.device)
+    # ------------------------------------------------------------ launch tuning
+    def set_tuning(self, form, blocks_per_cu):
+        f = (C.c_int32 * 2)(*form)
+        b = (C.c_int32 * 2)(*blocks_per_cu)
+        check(self.lib.lbem_set_tuning(self.h, f, b))
 
-    def adjoint_forward(self, nsteps: int, K: int, det_z: int, ws: torch.Tensor) -> torch.Tensor:
-        """Run nsteps with a checkpoint every K steps; return the detector loss (dev double [1])."""
+    def tuning(self):
+        f = (C.c_int32 * 2)()
+        b = (C.c_int32 * 2)()
+        check(self.lib.lbem_get_tuning(self.h, f, b))
+        return list(f), list(b)
+
+    def autotune(self, trial_steps: int = 10):
+        """Pick the fastest launch tuning on this lattice (state left unchanged)."""
+        backup = torch.empty(self.state_size(), dtype=torch.uint8, device=self.device)
+        check(self.lib.lbem_autotune(self.h, int(trial_steps), _ptr(backup)))
+        return self.tuning()
+
+    # ------------------------------------------------------------ adjoint
+    def adjoint_workspace(self, nsteps: int, K: int, keep: int = 1) -> torch.Tensor:
+        size = C.c_size_t()
+        check(self.lib.lbem_adjoint_workspace_size(C.byref(self._desc), int(nsteps), int(K), int(keep),
+                                                   C.byref(size)))
+        ws = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        self._adj_keep = int(keep)
+        return ws
+
+    def adjoint_forward(self, nsteps: int, K: int, det_z: int, ws: torch.Tensor,
+                        keep: Optional[int] = None) -> torch.Tensor:
+        """Run nsteps with a checkpoint every K steps (the last `keep` segments also
+        keep their E frames); return the detector loss (dev double [1])."""
+        keep = getattr(self, "_adj_keep", 1) if keep is None else keep
         loss = torch.zeros(1, dtype=torch.float64, device=self.device)
-        check(self.lib.lbem_adjoint_forward(self.h, int(nsteps), int(K), int(det_z), _ptr(ws),
+        check(self.lib.lbem_adjoint_forward(self.h, int(nsteps), int(K), int(keep), int(det_z), _ptr(ws),
                                             ws.numel(), _ptr(loss)))
         return loss
 

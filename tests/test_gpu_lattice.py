@@ -260,3 +260,29 @@ def test_unstable_and_invalid_media_rejected():
         lat.set_current_source([3, 3], [[0, 0, 1], [0, 0, 1]], 10.0)
     with pytest.raises(lbem.LbemError):
         lat.set_plane_source(4, (1, 0, 0), (0, 1, 0), 10.0)
+
+
+@pytest.mark.parametrize("model,storage", [("mm", "f32"), ("mm", "bf16"), ("hv", "f32")])
+def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage):
+    """Every (address form, blocks-per-CU cap) choice of the step kernel gives
+    the same bits; autotune leaves the state as it found it."""
+    shape = (128, 6, 10)
+    p = random_problem(model, shape, seed=21)
+    ref = None
+    for form in ((0, 0), (1, 1), (0, 1)):
+        for cap in ((0, 0), (2, 3), (4, 2)):
+            lat = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"], storage=storage)
+            lat.set_fields(p["E0"], p["B0"])
+            lat.set_currents(p["currents"])
+            lat.set_tuning(form, cap)
+            assert lat.tuning() == (list(form), list(cap))
+            lat.step(7)
+            E = lat.fields()[0].clone()
+            if ref is None:
+                ref = E
+            assert torch.equal(E, ref), (form, cap)
+    lat.step(3)
+    before = lat.fields()[0].clone()
+    lat.autotune(3)
+    assert torch.equal(lat.fields()[0], before)
+    assert lat.time == 10

@@ -2,6 +2,7 @@
 adjoint: its forward equals the C oracle, and its gradient equals central
 finite differences of its own loss (FP64, second order)."""
 import numpy as np
+import pytest
 import torch
 
 import oracle
@@ -18,26 +19,32 @@ def random_case(shape, seed):
     return d, {k: T(v) for k, v in d.items()}
 
 
-def test_torch_reference_equals_c_oracle():
+LOSS = {"mm": tr.detector_loss, "hv": tr.hv_detector_loss}
+FIELDS = {"mm": tr.fields, "hv": tr.hv_fields}
+
+
+@pytest.mark.parametrize("model", ["mm", "hv"])
+def test_torch_reference_equals_c_oracle(model):
     shape = (4, 3, 6)
     d, t = random_case(shape, 0)
-    P = oracle.Problem("mm", shape, eps_r=d["eps"], mu_r=d["mu"], sigma=d["sig"])
+    P = oracle.Problem(model, shape, eps_r=d["eps"], mu_r=d["mu"], sigma=d["sig"])
     f = oracle.init(P, d["E0"], d["B0"])
     out = oracle.run(P, f, 0, 7, det_z=2)
     E, B, _, _ = oracle.fields(P, f, 7)
-    L, ft = tr.detector_loss(t["eps"], t["sig"], t["mu"], t["E0"], t["B0"], 7, 2)
-    Et, Bt = tr.fields(ft, t["eps"], t["mu"], t["sig"])
+    L, ft = LOSS[model](t["eps"], t["sig"], t["mu"], t["E0"], t["B0"], 7, 2)
+    Et, Bt = FIELDS[model](ft, t["eps"], t["mu"], t["sig"])
     np.testing.assert_allclose(Et.numpy().reshape(3, -1), E, rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(Bt.numpy().reshape(3, -1), B, rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(L.item(), out["detector"].sum(), rtol=1e-12)
 
 
-def test_torch_reference_gradient_equals_finite_differences():
+@pytest.mark.parametrize("model", ["mm", "hv"])
+def test_torch_reference_gradient_equals_finite_differences(model):
     shape = (3, 2, 5)
     d, t = random_case(shape, 1)
     eps = t["eps"].clone().requires_grad_(True)
     sig = t["sig"].clone().requires_grad_(True)
-    L, _ = tr.detector_loss(eps, sig, t["mu"], t["E0"], t["B0"], 6, 3)
+    L, _ = LOSS[model](eps, sig, t["mu"], t["E0"], t["B0"], 6, 3)
     ge, gs = torch.autograd.grad(L, (eps, sig))
     h = 1e-5
     rng = np.random.default_rng(2)
@@ -52,7 +59,7 @@ def test_torch_reference_gradient_equals_finite_differences():
             else:
                 sp[k] += h
                 sm[k] -= h
-            Lp, _ = tr.detector_loss(ap, sp, t["mu"], t["E0"], t["B0"], 6, 3)
-            Lm, _ = tr.detector_loss(am, sm, t["mu"], t["E0"], t["B0"], 6, 3)
+            Lp, _ = LOSS[model](ap, sp, t["mu"], t["E0"], t["B0"], 6, 3)
+            Lm, _ = LOSS[model](am, sm, t["mu"], t["E0"], t["B0"], 6, 3)
             fd = (Lp - Lm).item() / (2 * h)
             assert abs(fd - g[k].item()) <= 1e-6 * max(1.0, abs(fd)), (which, k, fd, g[k].item())
