@@ -31,11 +31,16 @@ BYTES_PER_LU = {("mm", "f32"): 2 * 50 * 4 + 12, ("mm", "bf16"): 2 * 50 * 2 + 12,
                 ("hv", "f32"): 2 * 36 * 4 + 12, ("hv", "bf16"): 2 * 36 * 2 + 12}
 
 
+# sources the single-lattice step kernels are compiled from
+STEP_KERNEL_SOURCES = ("include/lbem.h", "paper_2309_08068_amd/csrc/lbem_common.hpp",
+                       "paper_2309_08068_amd/csrc/lbem_internal.hpp", "paper_2309_08068_amd/csrc/lbem_lattice.hip",
+                       "paper_2309_08068_amd/csrc/lbem_model.hpp", "paper_2309_08068_amd/csrc/lbem_util_kernels.hpp")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2309_08068_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, fn), "rb") as f:
+    for fn in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, fn), "rb") as f:
             h.update(fn.encode())
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -181,7 +186,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="lattice edge (the workload is n^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--only", default="", help="comma list of model_storage variants to time")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5000)
@@ -249,11 +254,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["frac"], 4),
                      "traffic": None if traffic is None else round(traffic / 1e9 / (head["kernel_ms"] * 1e-3), 1),
-                     "kernel": f"step_kernel<{head['model'].upper()}, {head['storage']}>",
+                     "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": head["bytes_per_lu"] * head["cells"],
+                     "kernel": f"row_step_kernel<{head['model'].upper()}, {head['storage']}>",
                      "bytes_per_lu": head["bytes_per_lu"], "kernel_ms": round(head["kernel_ms"], 4)},
         "variants": {k: {"mlups": round(v["mlups"], 1), "achieved_gbs": round(v["achieved_gbs"], 1),
                          "frac": round(v["frac"], 4), "kernel_ms": round(v["kernel_ms"], 4),
-                         "bytes_per_lu": v["bytes_per_lu"], "tuning": v["tuning"]} for k, v in results.items()},
+                         "bytes_per_lu": v["bytes_per_lu"], "tuning": v["tuning"],
+                         "traffic_gbs": None if v["traffic"] is None else round(v["traffic"] / 1e9 / (v["kernel_ms"] * 1e-3), 1)}
+                     for k, v in results.items()},
         "adjoint_over_forward": None,
     }
     if not args.no_batch:
