@@ -6,8 +6,11 @@ sponge on every face, soft point current J_z = sin(2 pi n / 40) at the centre,
 three field probes recorded every step).  One benchmark step is one time step
 of the whole lattice: gather with in-place streaming, collision, sources,
 scatter and the fused FP64 probe recording.  The headline value is the MM
-model with FP32 population storage; the HV model and BF16 storage are timed
-the same way and reported under "variants".
+model with FP32 population storage; the HV model, BF16 storage and the
+equilibrium-shifted BF16 storage are timed the same way and reported under
+"variants".  Further sections: the batched ragged 1-D multilayer workload, the
+adjoint on the 128 x 128 x 256 inverse-design lattice, the 384^3 precision
+sweep, and the FP64 oracle on the host cores.
 
 Prints one JSON line.  `value` is lattice updates per second (MLUPS) with the
 state already resident in HBM; `roofline` prices the step kernel against the
@@ -27,8 +30,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+# every population read and written once, 12 B of media; the equilibrium-shifted
+# formats also write and read one 16-byte record per cell
 BYTES_PER_LU = {("mm", "f32"): 2 * 50 * 4 + 12, ("mm", "bf16"): 2 * 50 * 2 + 12,
-                ("hv", "f32"): 2 * 36 * 4 + 12, ("hv", "bf16"): 2 * 36 * 2 + 12}
+                ("hv", "f32"): 2 * 36 * 4 + 12, ("hv", "bf16"): 2 * 36 * 2 + 12,
+                ("mm", "f16"): 2 * 50 * 2 + 12, ("hv", "f16"): 2 * 36 * 2 + 12,
+                ("mm", "bf16_shifted"): 2 * 50 * 2 + 12 + 32, ("hv", "bf16_shifted"): 2 * 36 * 2 + 12 + 32,
+                ("mm", "f16_shifted"): 2 * 50 * 2 + 12 + 32, ("hv", "f16_shifted"): 2 * 36 * 2 + 12 + 32}
 
 
 # sources the single-lattice step kernels are compiled from
@@ -163,6 +171,42 @@ def time_adjoint(model: str, steps: int, K: int, keep: int):
             "adjoint_total_s": round(adj, 4), "ratio": round(adj / fwd, 3), "finite_gradients": ok}
 
 
+def time_precision(model: str, n: int, steps: int):
+    """Precision sweep on the n^3 point dipole: every storage format runs the
+    same `steps` steps (after the autotuner); reports its throughput and the
+    relative L2 distance of E and B from the FP32-storage run (FP32 storage
+    itself is held to the FP64 oracle by the parity tests)."""
+    import torch
+    from paper_2309_08068_amd import inputs, lbem
+
+    w = inputs.dipole(model, n=n, steps=steps)
+    out, ref = {}, None
+    for storage in ("f32", "bf16", "f16", "bf16_shifted", "f16_shifted"):
+        lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=1024.0 if "f16" in storage else 0.0)
+        lat.autotune(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        E, B, _, _ = lat.fields()
+        del lat
+        r = {"mlups": round(w.n * steps / wall / 1e6, 1),
+             "frac": round(BYTES_PER_LU[(model, storage)] * w.n * steps / wall / 1e9 / HBM_PEAK_GBS, 4)}
+        if ref is None:
+            ref = (E, B)
+        else:
+            r["rel_l2_vs_f32"] = [round(float((X.double() - R.double()).norm() / R.double().norm()), 5)
+                                  for X, R in ((E, ref[0]), (B, ref[1]))]
+            del E, B
+        out[storage] = r
+        torch.cuda.empty_cache()
+        print(f"# precision {model} {n}^3 {storage}: {r}", file=sys.stderr, flush=True)
+    del ref
+    torch.cuda.empty_cache()
+    return {"workload": f"hertz_dipole_{n}^3_{model}_{steps}steps", "formats": out}
+
+
 def cpu_baseline(n: int, sample_steps: int):
     """The FP64 oracle on the host cores: a few steps of the same 256^3 MM dipole lattice."""
     import oracle
@@ -192,6 +236,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=1500)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 384^3 precision sweep")
+    ap.add_argument("--sweep-n", type=int, default=384)
+    ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: only `steps` steps of the --only variants, then a plain "
                          "copy of 1 GiB (torch copy_) three times as the calibration kernel of known size")
@@ -205,7 +252,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
-    variants = [("mm", "f32"), ("mm", "bf16"), ("hv", "f32"), ("hv", "bf16")]
+    variants = [("mm", "f32"), ("mm", "bf16"), ("hv", "f32"), ("hv", "bf16"), ("mm", "bf16_shifted"),
+                ("hv", "bf16_shifted")]
     if args.only:
         keep = set(args.only.split(","))
         variants = [v for v in variants if f"{v[0]}_{v[1]}" in keep]
@@ -215,6 +263,10 @@ def main():
             w = inputs.dipole(model, n=args.n, steps=args.steps)
             lat = lbem.lattice_from_workload(w, storage=storage)
             lat.set_probes(w.probes, args.steps + 1)
+            tuning = lat.autotune(10)
+            torch.cuda.synchronize()
+            print(f"# {model} {storage}: tuning {tuning}; timed region = the last {args.steps} step launches",
+                  file=sys.stderr, flush=True)
             lat.step(args.steps)
             torch.cuda.synchronize()
             print(f"# profiled {args.steps} steps of {model} {storage}", file=sys.stderr, flush=True)
@@ -277,6 +329,8 @@ def main():
         line["adjoint_over_forward"] = runs[0]["ratio"]
         for r in runs:
             print(f"# adjoint: {r}", file=sys.stderr, flush=True)
+    if not args.no_sweep:
+        line["precision_sweep"] = [time_precision(m, args.sweep_n, args.sweep_steps) for m in ("mm", "hv")]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -52,15 +52,34 @@ typedef enum { LBEM_MM = 0, LBEM_HV = 1 } lbem_model;
 /* Storage format of the populations.  Collision arithmetic is always FP32;
  * BF16/FP16 only change how populations are held in HBM (round to nearest
  * even on store).  FP16 multiplies by desc.storage_scale before rounding (and
- * divides after loading) so that small fields stay in the normal range. */
-typedef enum { LBEM_F32 = 0, LBEM_BF16 = 1, LBEM_F16 = 2 } lbem_storage;
+ * divides after loading) so that small fields stay in the normal range.
+ *
+ * The *_SHIFTED formats store each population relative to an equilibrium:
+ * a population leaving cell x is held as g_q = f'_q - phi_q(R_x), where R_x is
+ * a per-cell record written by the same step (E, B, eps_r and 1/mu_r of x,
+ * rounded to BF16, 16 bytes) and phi_q(R) is the field part of the equilibrium
+ * of eqs. (equilibriumsMiller) / (equilibriumHV) evaluated on that record
+ * (without the current term, which the paper's equilibria carry as v.J/16 for
+ * MM and as the source term T_i for HV; rest populations unshifted).  Since
+ * f' = 2 f_eq - f, g_q is the non-equilibrium part of the population, so the
+ * 16-bit rounding acts on a small remainder instead of the whole value.  The
+ * reader of population q at x adds phi_q(R_{x - v_q}) back.  Cost: 32 more
+ * bytes per lattice update (one record written, one read) and two record
+ * planes (2 x 16 B per cell) in the workspace.  Not available for batches. */
+typedef enum {
+    LBEM_F32 = 0,
+    LBEM_BF16 = 1,
+    LBEM_F16 = 2,
+    LBEM_BF16_SHIFTED = 3,
+    LBEM_F16_SHIFTED = 4
+} lbem_storage;
 
 typedef struct {
     int32_t model;         /* lbem_model */
     int32_t storage;       /* lbem_storage */
     int32_t nx, ny, nz;    /* lattice size, each >= 1 */
     int32_t reserved;      /* must be 0 */
-    double storage_scale;  /* FP16 only: power of two > 0 (0 means 1); ignored otherwise */
+    double storage_scale;  /* FP16 formats only: power of two > 0 (0 means 1); ignored otherwise */
 } lbem_desc;
 
 typedef struct lbem_lattice lbem_lattice;
@@ -78,7 +97,8 @@ const char *lbem_last_error(void);
 /* Bytes of device workspace lbem_create needs for this descriptor. */
 lbem_status lbem_workspace_size(const lbem_desc *desc, size_t *bytes);
 
-/* Bytes of one population state (what save_state writes). */
+/* Bytes of one population state (what save_state writes): the populations,
+ * and for the shifted formats also the record plane the next step reads. */
 lbem_status lbem_state_size(const lbem_desc *desc, size_t *bytes);
 
 /* Create a lattice.

@@ -314,7 +314,7 @@ struct AdjLayout {
 AdjLayout adj_layout(const lbem_desc *d, int64_t nsteps, int32_t K, int32_t keep) {
     AdjLayout L{};
     const size_t N = size_t(d->nx) * d->ny * d->nz;
-    L.state_bytes = N * (d->model == LBEM_MM ? 50 : 36) * (d->storage == LBEM_F32 ? 4 : 2);
+    L.state_bytes = state_bytes(d);
     L.S = (nsteps + K - 1) / K;
     L.keep = std::max<int64_t>(1, std::min<int64_t>(keep, L.S));
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };

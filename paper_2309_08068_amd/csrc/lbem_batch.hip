@@ -163,7 +163,8 @@ BatchLayout batch_layout(int model, int storage, int32_t n, size_t total) {
 
 lbem_status check_offsets(int32_t model, int32_t storage, int32_t n, const int64_t *offsets) {
     if (model != LBEM_MM && model != LBEM_HV) return fail(LBEM_EINVAL, "unknown model %d", model);
-    if (storage < LBEM_F32 || storage > LBEM_F16) return fail(LBEM_EINVAL, "unknown storage %d", storage);
+    if (storage < LBEM_F32 || storage > LBEM_F16)
+        return fail(LBEM_EINVAL, "storage %d is not available for batches (plain FP32, BF16 or FP16 only)", storage);
     if (n < 1) return fail(LBEM_EINVAL, "need at least one instance");
     if (!offsets) return fail(LBEM_EINVAL, "offsets is NULL");
     if (offsets[0] != 0) return fail(LBEM_EINVAL, "offsets[0] must be 0");

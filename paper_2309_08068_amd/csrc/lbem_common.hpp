@@ -29,6 +29,7 @@ __device__ __forceinline__ void put(T *p, T v) {
 struct StF32 {
     using T = float;
     static constexpr int kBytes = 4;
+    static constexpr bool kShift = false;
     __device__ static float cvt(T r, float) { return r; }
     __device__ static T pack(float v, float) { return v; }
     template <bool NT = false>
@@ -40,6 +41,7 @@ struct StF32 {
 struct StBF16 {
     using T = uint16_t;
     static constexpr int kBytes = 2;
+    static constexpr bool kShift = false;
     __device__ static float cvt(T r, float) { return __uint_as_float(uint32_t(r) << 16); }
     // round to nearest, ties to even (inputs are finite)
     __device__ static T pack(float v, float) {
@@ -56,6 +58,7 @@ struct StBF16 {
 struct StF16 {
     using T = _Float16;
     static constexpr int kBytes = 2;
+    static constexpr bool kShift = false;
     // values are held multiplied by a power-of-two scale
     __device__ static float cvt(T r, float inv_scale) { return float(r) * inv_scale; }
     __device__ static T pack(float v, float scale) { return _Float16(v * scale); }
@@ -63,6 +66,15 @@ struct StF16 {
     __device__ static float load(const T *p, uint32_t i, float inv) { return cvt(raw<T, NT>(p + i), inv); }
     template <bool NT = false>
     __device__ static void store(T *p, uint32_t i, float v, float scale) { put<T, NT>(p + i, pack(v, scale)); }
+};
+
+// The same 16-bit formats holding equilibrium-shifted populations (see Shift
+// in lbem_model.hpp); the kernels add the per-cell record traffic.
+struct StBF16S : StBF16 {
+    static constexpr bool kShift = true;
+};
+struct StF16S : StF16 {
+    static constexpr bool kShift = true;
 };
 
 // ------------------------------------------------------------ addressing
@@ -146,6 +158,27 @@ __device__ __forceinline__ void late_addresses(Nbr &nb, P *&base, float after) {
                  : "v"(after));
 }
 
+// ------------------------------------------------------------ shifted storage
+// Add back phi_q(R_{x - v_q}) to freshly gathered shifted populations; cell_of
+// maps a velocity offset (dx, dy, dz) to the neighbour's cell index.
+template <class M, class F>
+__device__ __forceinline__ void unshift(float (&f)[M::Q], const u32x4 *__restrict__ rec, F &&cell_of) {
+    shift_all<M>(f, 1.f, [&](int k) {
+        return rec_unpack(rec[cell_of(-Shift<M>::vel(k, 0), -Shift<M>::vel(k, 1), -Shift<M>::vel(k, 2))]);
+    });
+}
+
+// Subtract phi_q(R_x) from the post-collision populations of this cell and
+// write its record (non-temporal: it is read again only in the next step).
+template <class M>
+__device__ __forceinline__ void shift_out(float (&f)[M::Q], const float E[3], const float B[3], float eps_r,
+                                          float mu_r, u32x4 *__restrict__ rec, uint32_t c, bool store) {
+    Rec r;
+    const u32x4 w = rec_pack(E, B, eps_r, 1.0f / mu_r, r);
+    if (store) __builtin_nontemporal_store(w, rec + c);
+    shift_all<M>(f, -1.f, [&](int) { return r; });
+}
+
 // ------------------------------------------------------------ row form
 // Number of populations of M whose velocity has a non-zero x component.
 template <class M>
@@ -186,6 +219,10 @@ struct RowIO {
     }
     // store addresses formed after the collision (see late_addresses)
     __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo) : "v"(after)); }
+    // cell index of x + (dx, dy, dz), |d| <= 1, periodic
+    __device__ uint32_t cell(int dx, int dy, int dz) const {
+        return (yr[dy + 1] + ny * zr[dz + 1]) * uint32_t(RB) + (x + uint32_t(RB + dx)) % uint32_t(RB);
+    }
 
     template <int ODD>
     __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale) const {

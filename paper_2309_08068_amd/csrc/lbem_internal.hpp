@@ -11,12 +11,25 @@ namespace lbem {
 
 // Byte offsets of the regions of a lattice workspace.
 struct WsLayout {
-    size_t pop, eps, mu, sig, en_part, det_part, src_blk, src_cell, src_J0, prb_blk, prb_cell, prb_slot, flags;
+    size_t pop, rec, eps, mu, sig, en_part, det_part, src_blk, src_cell, src_J0, prb_blk, prb_cell, prb_slot, flags;
     size_t det_cap;  // detector partial slots
     size_t total;
 };
 
 WsLayout layout(const lbem_desc *d);
+
+// Equilibrium-shifted storage formats keep two planes of 16-byte per-cell
+// records (the step at time t reads plane (t + 1) & 1 and writes plane t & 1).
+inline bool shifted(int32_t storage) { return storage == LBEM_BF16_SHIFTED || storage == LBEM_F16_SHIFTED; }
+inline size_t pop_bytes(const lbem_desc *d) {
+    return size_t(d->nx) * d->ny * d->nz * (d->model == LBEM_MM ? 50 : 36) * (d->storage == LBEM_F32 ? 4 : 2);
+}
+constexpr size_t kRecBytes = 16;
+// Bytes of one saved state: the populations, and for the shifted formats the
+// record plane the next step reads.
+inline size_t state_bytes(const lbem_desc *d) {
+    return pop_bytes(d) + (shifted(d->storage) ? size_t(d->nx) * d->ny * d->nz * kRecBytes : 0);
+}
 
 // x extent handled by the row form of the step kernel (one block per x-row),
 // or 0 when the lattice uses the generic form.
@@ -53,6 +66,8 @@ struct StepArgs {
     double *en_part;
     // if set, E of the collided state is written here ([3][N] floats)
     float *E_out;
+    // shifted storage: the two record planes (uint4 [N] each), else null
+    void *rec[2];
 };
 
 

@@ -42,6 +42,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     if (live) gather<M, ODD, ST>(pop, N, nb, f, a.inv_scale);
     else
         for (int q = 0; q < M::Q; ++q) f[q] = 0.f;
+    if constexpr (ST::kShift)
+        if (live)
+            unshift<M>(f, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]),
+                       [&](int dx, int dy, int dz) { return nb.at(dx, dy, dz); });
 
     CellMedia m{a.eps[cc], a.mu[cc], a.sig[cc]};
     float Js[3] = {0.f, 0.f, 0.f};
@@ -56,7 +60,11 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     }
     CellFields o;
     Cell<M>::collide(f, m, Js, o);
-    if (int32_t(z) == a.plane_z) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
+    const bool plane = int32_t(z) == a.plane_z;
+    if (plane) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
+    if constexpr (ST::kShift)
+        shift_out<M>(f, plane ? a.Eimp : o.E, plane ? a.Bimp : o.B, m.eps_r, m.mu_r,
+                     static_cast<u32x4 *>(a.rec[ODD ? 1 : 0]), c, live);
     if (live) {
         // store addresses formed after the collision (see late_addresses)
         Nbr nb2 = nb;
@@ -116,6 +124,9 @@ __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
     RowIO<M, ST, RB> io(a.pop, N, a.ny, a.nz, row);
     float f[M::Q];
     io.template gather<ODD>(f, sh, a.inv_scale);
+    if constexpr (ST::kShift)
+        unshift<M>(f, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]),
+                   [&](int dx, int dy, int dz) { return io.cell(dx, dy, dz); });
 
     CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
     float Js[3] = {0.f, 0.f, 0.f};
@@ -130,7 +141,11 @@ __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
     }
     CellFields o;
     Cell<M>::collide(f, m, Js, o);
-    if (int32_t(z) == a.plane_z) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
+    const bool plane = int32_t(z) == a.plane_z;
+    if (plane) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
+    if constexpr (ST::kShift)
+        shift_out<M>(f, plane ? a.Eimp : o.E, plane ? a.Bimp : o.B, m.eps_r, m.mu_r,
+                     static_cast<u32x4 *>(a.rec[ODD ? 1 : 0]), c, true);
 
     if (LATE) io.late(f[0]);
     io.template scatter<ODD>(f, sh, a.scale);
@@ -176,6 +191,7 @@ struct ObsArgs {
     float src_w;
     float *E, *B, *D, *H;
     double *en_part;
+    const void *rec;  // shifted storage: the record plane this state's reader uses
 };
 
 // Reported fields of the current state (no update).
@@ -192,6 +208,8 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
     const size_t N = a.N;
     float f[M::Q];
     gather<M, ODD, ST>(static_cast<const typename ST::T *>(a.pop), N, nb, f, a.inv_scale);
+    if constexpr (ST::kShift)
+        unshift<M>(f, static_cast<const u32x4 *>(a.rec), [&](int dx, int dy, int dz) { return nb.at(dx, dy, dz); });
     CellMedia m{a.eps[cc], a.mu[cc], a.sig[cc]};
     float Js[3] = {0.f, 0.f, 0.f};
     if (a.src_blk) {
@@ -223,10 +241,13 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
     }
 }
 
-// f := f_eq(E, B, J = 0) in natural layout.
+// f := f_eq(E, B, J = 0) in natural layout.  Shifted storage: slot (q, c)
+// holds f_q - phi_q(R_{c - v_q}) with the records of the same fields, which
+// init_record_kernel has written to the plane the first step reads.
 template <class M, class ST>
 __global__ __launch_bounds__(kBlock) void init_kernel(void *pop, const float *eps, const float *mu, const float *E,
-                                                      const float *B, uint32_t N, float scale) {
+                                                      const float *B, uint32_t nx, uint32_t ny, uint32_t nz,
+                                                      uint32_t N, float scale, const void *rec) {
     const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= N) return;
     CellMedia m{eps[c], mu[c], 0.f};
@@ -234,9 +255,28 @@ __global__ __launch_bounds__(kBlock) void init_kernel(void *pop, const float *ep
     const float b[3] = {B[c], B[size_t(N) + c], B[2 * size_t(N) + c]};
     float f[M::Q];
     Cell<M>::equilibrium(f, m, e, b);
+    if constexpr (ST::kShift) {
+        const uint32_t nxy = nx * ny;
+        const uint32_t z = c / nxy, rem = c - z * nxy, y = rem / nx, x = rem - y * nx;
+        const Nbr nb = make_nbr(c, x, y, z, nx, ny, nz);
+        float g[M::Q];
+        for (int q = 0; q < M::Q; ++q) g[q] = 0.f;
+        unshift<M>(g, static_cast<const u32x4 *>(rec), [&](int dx, int dy, int dz) { return nb.at(dx, dy, dz); });
+        for (int q = 0; q < M::Q; ++q) f[q] -= g[q];
+    }
     auto *p = static_cast<typename ST::T *>(pop);
 #pragma unroll
     for (int q = 0; q < M::Q; ++q) ST::store(p + size_t(q) * N, c, f[q], scale);
+}
+
+__global__ __launch_bounds__(kBlock) void init_record_kernel(void *rec, const float *eps, const float *mu,
+                                                             const float *E, const float *B, uint32_t N) {
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= N) return;
+    const float e[3] = {E[c], E[size_t(N) + c], E[2 * size_t(N) + c]};
+    const float b[3] = {B[c], B[size_t(N) + c], B[2 * size_t(N) + c]};
+    Rec r;
+    static_cast<u32x4 *>(rec)[c] = rec_pack(e, b, eps[c], 1.0f / mu[c], r);
 }
 
 // ============================================================== host side
@@ -262,15 +302,18 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+bool is_f16(int st) { return st == LBEM_F16 || st == LBEM_F16_SHIFTED; }
+
 lbem_status check_desc(const lbem_desc *d) {
     if (!d) return fail(LBEM_EINVAL, "desc is NULL");
     if (d->model != LBEM_MM && d->model != LBEM_HV) return fail(LBEM_EINVAL, "unknown model %d", d->model);
-    if (d->storage < LBEM_F32 || d->storage > LBEM_F16) return fail(LBEM_EINVAL, "unknown storage %d", d->storage);
+    if (d->storage < LBEM_F32 || d->storage > LBEM_F16_SHIFTED)
+        return fail(LBEM_EINVAL, "unknown storage %d", d->storage);
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(LBEM_EINVAL, "lattice size must be >= 1 on every axis");
     if (d->reserved != 0) return fail(LBEM_EINVAL, "reserved field must be 0");
     const double n = double(d->nx) * d->ny * d->nz;
     if (n >= 2147483648.0) return fail(LBEM_EINVAL, "lattice has %.0f cells; the limit is 2^31 - 1", n);
-    if (d->storage == LBEM_F16 && d->storage_scale != 0.0) {
+    if (is_f16(d->storage) && d->storage_scale != 0.0) {
         int ex;
         const double m = std::frexp(d->storage_scale, &ex);
         if (!(d->storage_scale > 0.0) || m != 0.5) return fail(LBEM_EINVAL, "storage_scale must be a power of two");
@@ -302,6 +345,7 @@ WsLayout layout(const lbem_desc *d) {
         return o;
     };
     L.pop = take(N * model_q(d->model) * storage_bytes(d->storage));
+    L.rec = take(shifted(d->storage) ? 2 * N * kRecBytes : 0);
     L.eps = take(N * 4);
     L.mu = take(N * 4);
     L.sig = take(N * 4);
@@ -338,7 +382,7 @@ lbem_status lbem_state_size(const lbem_desc *desc, size_t *bytes) {
     lbem_status st = check_desc(desc);
     if (st) return st;
     if (!bytes) return fail(LBEM_EINVAL, "bytes is NULL");
-    *bytes = size_t(desc->nx) * desc->ny * desc->nz * model_q(desc->model) * storage_bytes(desc->storage);
+    *bytes = state_bytes(desc);
     return LBEM_OK;
 }
 
@@ -363,7 +407,7 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     lat->bu = row_block(desc) ? row_block(desc) : uint32_t(kBlock);
     lat->nblocks = uint32_t((size_t(lat->N) + lat->bu - 1) / lat->bu);
     lat->nobs = grid_for(lat->N);
-    lat->scale = (desc->storage == LBEM_F16 && desc->storage_scale != 0.0) ? float(desc->storage_scale) : 1.0f;
+    lat->scale = (is_f16(desc->storage) && desc->storage_scale != 0.0) ? float(desc->storage_scale) : 1.0f;
     lat->inv_scale = 1.0f / lat->scale;
     lat->stream = static_cast<hipStream_t>(stream);
     lat->ws = static_cast<char *>(workspace);
@@ -390,7 +434,8 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     const size_t tail = L.total - L.en_part;
     hipLaunchKernelGGL(zero_bytes, dim3(grid_for(tail / 4)), dim3(kBlock), 0, s,
                        reinterpret_cast<uint32_t *>(lat->ws + L.en_part), tail / 4);
-    const size_t popw = size_t(lat->N) * lat->Q * lat->sbytes / 4;
+    // populations and record planes (zero records: phi = 0, so the state is zero)
+    const size_t popw = (L.eps - L.pop) / 4;
     hipLaunchKernelGGL(zero_bytes, dim3(grid_for(popw)), dim3(kBlock), 0, s,
                        reinterpret_cast<uint32_t *>(lat->ws + L.pop), popw);
     int32_t *flags = reinterpret_cast<int32_t *>(lat->ws + L.flags);
@@ -424,11 +469,21 @@ lbem_status lbem_set_stream(lbem_lattice *lat, void *stream) {
     return LBEM_OK;
 }
 
+// record plane read by the step at time level t (shifted storage)
+static char *read_rec(const lbem_lattice *lat, int64_t t) {
+    return lat->ws + lat->L.rec + size_t((t + 1) & 1) * lat->N * kRecBytes;
+}
+
 template <class M, class ST>
 static void launch_init(lbem_lattice *lat, const float *E, const float *B) {
-    hipLaunchKernelGGL((init_kernel<M, ST>), dim3(lat->nobs), dim3(kBlock), 0, lat->stream, lat->ws + lat->L.pop,
-                       reinterpret_cast<const float *>(lat->ws + lat->L.eps),
-                       reinterpret_cast<const float *>(lat->ws + lat->L.mu), E, B, lat->N, lat->scale);
+    const float *eps = reinterpret_cast<const float *>(lat->ws + lat->L.eps);
+    const float *mu = reinterpret_cast<const float *>(lat->ws + lat->L.mu);
+    char *rec = ST::kShift ? read_rec(lat, 0) : nullptr;
+    if (ST::kShift)
+        hipLaunchKernelGGL(init_record_kernel, dim3(lat->nobs), dim3(kBlock), 0, lat->stream, rec, eps, mu, E, B, lat->N);
+    hipLaunchKernelGGL((init_kernel<M, ST>), dim3(lat->nobs), dim3(kBlock), 0, lat->stream, lat->ws + lat->L.pop, eps,
+                       mu, E, B, uint32_t(lat->d.nx), uint32_t(lat->d.ny), uint32_t(lat->d.nz), lat->N, lat->scale,
+                       rec);
 }
 
 template <class M>
@@ -436,7 +491,9 @@ static void dispatch_init(lbem_lattice *lat, const float *E, const float *B) {
     switch (lat->d.storage) {
         case LBEM_F32: launch_init<M, StF32>(lat, E, B); break;
         case LBEM_BF16: launch_init<M, StBF16>(lat, E, B); break;
-        default: launch_init<M, StF16>(lat, E, B); break;
+        case LBEM_F16: launch_init<M, StF16>(lat, E, B); break;
+        case LBEM_BF16_SHIFTED: launch_init<M, StBF16S>(lat, E, B); break;
+        default: launch_init<M, StF16S>(lat, E, B); break;
     }
 }
 
@@ -614,7 +671,9 @@ static const void *step_kernel_ptr_st(const lbem_lattice *lat, int form) {
     switch (lat->d.storage) {
         case LBEM_F32: return step_kernel_ptr<M, ODD, StF32>(rb, form);
         case LBEM_BF16: return step_kernel_ptr<M, ODD, StBF16>(rb, form);
-        default: return step_kernel_ptr<M, ODD, StF16>(rb, form);
+        case LBEM_F16: return step_kernel_ptr<M, ODD, StF16>(rb, form);
+        case LBEM_BF16_SHIFTED: return step_kernel_ptr<M, ODD, StBF16S>(rb, form);
+        default: return step_kernel_ptr<M, ODD, StF16S>(rb, form);
     }
 }
 
@@ -674,6 +733,10 @@ StepArgs lbem::base_step_args(lbem_lattice *lat) {
     }
     a.plane_z = lat->plane_z;
     a.det_z = -1;
+    if (shifted(lat->d.storage)) {
+        a.rec[0] = lat->ws + L.rec;
+        a.rec[1] = lat->ws + L.rec + size_t(lat->N) * kRecBytes;
+    }
     return a;
 }
 
@@ -739,7 +802,9 @@ static void dispatch_obs_storage(const lbem_lattice *lat, const ObsArgs &a) {
     switch (lat->d.storage) {
         case LBEM_F32: launch_obs<M, ODD, StF32>(a, lat->nobs, lat->stream); break;
         case LBEM_BF16: launch_obs<M, ODD, StBF16>(a, lat->nobs, lat->stream); break;
-        default: launch_obs<M, ODD, StF16>(a, lat->nobs, lat->stream); break;
+        case LBEM_F16: launch_obs<M, ODD, StF16>(a, lat->nobs, lat->stream); break;
+        case LBEM_BF16_SHIFTED: launch_obs<M, ODD, StBF16S>(a, lat->nobs, lat->stream); break;
+        default: launch_obs<M, ODD, StF16S>(a, lat->nobs, lat->stream); break;
     }
 }
 
@@ -767,6 +832,7 @@ static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, floa
     a.D = D;
     a.H = H;
     a.en_part = en_part;
+    if (shifted(lat->d.storage)) a.rec = read_rec(lat, lat->t);
     const int odd = int(lat->t & 1);
     if (lat->d.model == LBEM_MM) {
         if (odd) dispatch_obs_storage<MM, 1>(lat, a);
@@ -792,18 +858,29 @@ lbem_status lbem_energy(lbem_lattice *lat, double *out) {
     return hip_check(hipGetLastError(), "energy sum");
 }
 
+// state = populations, then (shifted storage) the record plane the next step reads
+static lbem_status copy_state(lbem_lattice *lat, void *dst, const void *src, int64_t t) {
+    const size_t pb = pop_bytes(&lat->d), rb = state_bytes(&lat->d) - pb;
+    char *pop = lat->ws + lat->L.pop, *rec = read_rec(lat, t);
+    char *d = static_cast<char *>(dst);
+    const char *sr = static_cast<const char *>(src);
+    lbem_status st = hip_check(hipMemcpyAsync(d ? d : pop, d ? pop : sr, pb, hipMemcpyDeviceToDevice, lat->stream),
+                               "copy state");
+    if (!st && rb)
+        st = hip_check(hipMemcpyAsync(d ? d + pb : rec, d ? rec : sr + pb, rb, hipMemcpyDeviceToDevice, lat->stream),
+                       "copy records");
+    return st;
+}
+
 lbem_status lbem_save_state(lbem_lattice *lat, void *dst) {
     if (!lat || !dst) return fail(LBEM_EINVAL, "null argument");
-    const size_t bytes = size_t(lat->N) * lat->Q * lat->sbytes;
-    return hip_check(hipMemcpyAsync(dst, lat->ws + lat->L.pop, bytes, hipMemcpyDeviceToDevice, lat->stream), "save");
+    return copy_state(lat, dst, nullptr, lat->t);
 }
 
 lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t) {
     if (!lat || !src) return fail(LBEM_EINVAL, "null argument");
     if (t < 0) return fail(LBEM_EINVAL, "time level < 0");
-    const size_t bytes = size_t(lat->N) * lat->Q * lat->sbytes;
-    lbem_status st =
-        hip_check(hipMemcpyAsync(lat->ws + lat->L.pop, src, bytes, hipMemcpyDeviceToDevice, lat->stream), "load");
+    lbem_status st = copy_state(lat, nullptr, src, t);
     if (st) return st;
     lat->t = t;
     return LBEM_OK;
@@ -835,9 +912,7 @@ lbem_status lbem_get_tuning(lbem_lattice *lat, int32_t *form, int32_t *blocks_pe
 lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup) {
     if (!lat || !backup) return fail(LBEM_EINVAL, "null argument");
     if (trial_steps < 1) return fail(LBEM_EINVAL, "trial_steps must be >= 1");
-    const size_t bytes = size_t(lat->N) * lat->Q * lat->sbytes;
-    lbem_status st =
-        hip_check(hipMemcpyAsync(backup, lat->ws + lat->L.pop, bytes, hipMemcpyDeviceToDevice, lat->stream), "backup");
+    lbem_status st = copy_state(lat, backup, nullptr, lat->t);
     if (st) return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     st = hip_check(hipEventCreate(&e0), "event");
@@ -880,7 +955,6 @@ lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup) 
     }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
-    lbem_status st2 =
-        hip_check(hipMemcpyAsync(lat->ws + lat->L.pop, backup, bytes, hipMemcpyDeviceToDevice, lat->stream), "restore");
+    lbem_status st2 = copy_state(lat, nullptr, backup, lat->t);
     return st ? st : st2;
 }

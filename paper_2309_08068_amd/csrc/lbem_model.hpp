@@ -304,6 +304,114 @@ __device__ __forceinline__ void hv_field_equilibrium(float (&f)[36], const CellM
     hv_eq_dir<5>(f, D, B, E, H);
 }
 
+// ---------------------------------------------------------------- shift
+// Equilibrium-shifted 16-bit storage.  A population leaving cell x is stored
+// as g_q = f'_q - phi_q(R_x), where R_x is a per-cell record of the emitting
+// cell (E, B, eps_r, 1/mu_r, each rounded to BF16) and phi_q(R) is the
+// field part of the equilibrium of q for that record (the current term
+// v.J/16 of MM and the HV source term are left out, and the rest populations
+// are not shifted).  Since f' = 2 f_eq - f, f'_q - f_eq_q = f_eq_q - f_q is the
+// non-equilibrium part, typically a small fraction of f_q on smooth fields, so
+// the 16-bit rounding error shrinks by that fraction.  The reader of
+// population q at x adds phi_q(R_{x - v_q}) back, evaluated by the same code
+// on the same rounded record.
+//
+// Record layout: 8 BF16 values, rec[0..2] = E, rec[3..5] = B, rec[6] = eps_r,
+// rec[7] = 1 / mu_r (16 bytes, one aligned vector access).
+struct Rec {
+    float E[3], B[3], eps, imu;
+};
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_rn(float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Round a record to BF16; returns the packed 16 bytes and the rounded values.
+__device__ __forceinline__ u32x4 rec_pack(const float E[3], const float B[3], float eps, float imu, Rec &r) {
+    const uint16_t h[8] = {bf16_rn(E[0]), bf16_rn(E[1]), bf16_rn(E[2]), bf16_rn(B[0]),
+                           bf16_rn(B[1]), bf16_rn(B[2]), bf16_rn(eps), bf16_rn(imu)};
+    for (int a = 0; a < 3; ++a) {
+        r.E[a] = bf16_f(h[a]);
+        r.B[a] = bf16_f(h[3 + a]);
+    }
+    r.eps = bf16_f(h[6]);
+    r.imu = bf16_f(h[7]);
+    u32x4 u;
+    u.x = uint32_t(h[0]) | uint32_t(h[1]) << 16;
+    u.y = uint32_t(h[2]) | uint32_t(h[3]) << 16;
+    u.z = uint32_t(h[4]) | uint32_t(h[5]) << 16;
+    u.w = uint32_t(h[6]) | uint32_t(h[7]) << 16;
+    return u;
+}
+
+__device__ __forceinline__ Rec rec_unpack(u32x4 u) {
+    Rec r;
+    r.E[0] = bf16_f(u.x & 0xffffu);
+    r.E[1] = bf16_f(u.x >> 16);
+    r.E[2] = bf16_f(u.y & 0xffffu);
+    r.B[0] = bf16_f(u.y >> 16);
+    r.B[1] = bf16_f(u.z & 0xffffu);
+    r.B[2] = bf16_f(u.z >> 16);
+    r.eps = bf16_f(u.w & 0xffffu);
+    r.imu = bf16_f(u.w >> 16);
+    return r;
+}
+
+// Per model: the distinct moving velocities k (every shifted population
+// belongs to exactly one) and f[q] += s * phi_q(R) over the populations of k.
+template <class M>
+struct Shift;
+template <>
+struct Shift<MM> {
+    static constexpr int kNV = 12;  // k = p * 4 + i; populations 2k, 2k+1, 24+2k, 24+2k+1
+    __host__ __device__ static constexpr int vel(int k, int a) { return kMMV[k / 4][k % 4][a]; }
+    template <int K>
+    __device__ static void add(float (&f)[50], const Rec &r, float s) {
+        constexpr int p = K / 4, i = K % 4;
+        float ee = 0.f, bb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (mm_e2(p, i, a) != 0) ee += mm_e2(p, i, a) > 0 ? r.E[a] : -r.E[a];
+            if (kMMB[p][a] != 0) bb += kMMB[p][a] > 0 ? r.B[a] : -r.B[a];
+        }
+        // E.e_{i0} = ee / 2; f0_eq = eps/4 E.e + B.b/(8 mu), f1_eq = E.e/4 + B.b/8
+        const float u0 = s * (0.125f * r.eps * ee + 0.125f * r.imu * bb);
+        const float u1 = s * (0.125f * ee + 0.125f * bb);
+        f[2 * K] += u0;
+        f[2 * K + 1] -= u0;
+        f[24 + 2 * K] += u1;
+        f[24 + 2 * K + 1] -= u1;
+    }
+};
+template <>
+struct Shift<HV> {
+    static constexpr int kNV = 6;  // k = i; populations 3i + a, 18 + 3i + a
+    __host__ __device__ static constexpr int vel(int k, int a) { return kHVV[k][a]; }
+    template <int K>
+    __device__ static void add(float (&f)[36], const Rec &r, float s) {
+        // e_eq = (3 eps_r E - v x B / mu_r) / 6,  h_eq = (B + 3 v x E) / 6
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            f[3 * K + a] += s * (0.5f * r.eps * r.E[a] - (1.f / 6.f) * r.imu * hv_vcross<K>(r.B, a));
+            f[18 + 3 * K + a] += s * ((1.f / 6.f) * r.B[a] + 0.5f * hv_vcross<K>(r.E, a));
+        }
+    }
+};
+
+// f += s * phi(R_k) for every velocity k, with R_k produced by rec_of(k).
+template <class M, int K = 0, class F>
+__device__ __forceinline__ void shift_all(float (&f)[M::Q], float s, F &&rec_of) {
+    if constexpr (K < Shift<M>::kNV) {
+        const Rec r = rec_of(K);
+        Shift<M>::template add<K>(f, r, s);
+        shift_all<M, K + 1>(f, s, rec_of);
+    }
+}
+
 // model dispatch
 template <class M>
 struct Cell;

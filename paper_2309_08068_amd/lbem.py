@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbem.so")
 
 MODEL = {"mm": 0, "hv": 1}
-STORAGE = {"f32": 0, "bf16": 1, "f16": 2}
+STORAGE = {"f32": 0, "bf16": 1, "f16": 2, "bf16_shifted": 3, "f16_shifted": 4}
 NQ = {"mm": 50, "hv": 36}
 STATUS = {0: "LBEM_OK", -1: "LBEM_EINVAL", -2: "LBEM_ENOMEM", -3: "LBEM_EHIP", -4: "LBEM_EUNSTABLE",
           -5: "LBEM_ESTATE", -6: "LBEM_ENOTFINITE"}

@@ -65,9 +65,30 @@ def test_workspace_size_grows_with_model_and_storage(lib):
     assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0 and out.value == n * 50 * 2
 
 
+@pytest.mark.parametrize("storage,q", [("bf16_shifted", 50), ("f16_shifted", 50)])
+def test_shifted_storage_sizes(lib, storage, q):
+    """Equilibrium-shifted formats: 16-bit populations plus two planes of
+    16-byte records in the workspace; a saved state holds one record plane."""
+    n = 16 ** 3
+    st, b_sh = ws("mm", (16, 16, 16), storage)
+    _, b_bf = ws("mm", (16, 16, 16), "bf16")
+    assert st == 0 and b_sh >= b_bf + 2 * 16 * n
+    out = C.c_size_t()
+    d = lbem.desc("mm", (16, 16, 16), storage)
+    assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0 and out.value == n * q * 2 + 16 * n
+
+
+def test_batch_rejects_shifted_storage(lib):
+    off = (C.c_int64 * 3)(0, 10, 30)
+    out = C.c_size_t()
+    for storage in ("bf16_shifted", "f16_shifted"):
+        assert lib.lbem_batch_workspace_size(0, lbem.STORAGE[storage], 2, off, C.byref(out)) == -1
+        assert b"batches" in lib.lbem_last_error()
+
+
 @pytest.mark.parametrize("kw", [dict(shape=(0, 4, 4)), dict(shape=(4, -1, 4)), dict(reserved=1),
                                 dict(storage="f16", scale=3.0), dict(storage="f16", scale=-2.0),
-                                dict(shape=(2048, 1024, 1024))])
+                                dict(storage="f16_shifted", scale=3.0), dict(shape=(2048, 1024, 1024))])
 def test_bad_descriptors_rejected(lib, kw):
     st, _ = ws(**kw)
     assert st == -1

@@ -95,6 +95,47 @@ def test_random_state_parity(model, shape, steps):
         assert rel(g[k], o[k]) < TOL, (k, rel(g[k], o[k]))
 
 
+# equilibrium-shifted 16-bit storage on random (non-smooth) states: the
+# non-equilibrium remainder is then as large as the population itself, so the
+# error is that of plain 16-bit storage; a wrong neighbour record in the
+# decode would instead leave O(1) errors
+SHIFTED_BOUND = {"bf16_shifted": 2e-2, "f16_shifted": 3e-3}
+
+
+@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("steps", [8, 9])
+@pytest.mark.parametrize("storage", ["bf16_shifted", "f16_shifted"])
+def test_shifted_storage_random_state(model, shape, steps, storage):
+    """Shifted storage with random media, fields, soft currents and a hard plane
+    source, both parities, generic and row form, against the FP64 oracle."""
+    print(f"case {model} {shape} {steps} {storage}", flush=True)
+    p = random_problem(model, shape, seed=zlib.crc32(repr((model, shape, steps)).encode()), plane=True)
+    g, _ = run_gpu(model, shape, p, steps, storage=storage)
+    o = run_oracle(model, shape, p, steps)
+    for k in "EBDH":
+        assert rel(g[k], o[k]) < SHIFTED_BOUND[storage], (k, rel(g[k], o[k]))
+
+
+@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("plain,shifted,scale", [("bf16", "bf16_shifted", 0.0), ("f16", "f16_shifted", 256.0)])
+def test_shifted_storage_beats_plain_on_smooth_fields(model, plain, shifted, scale):
+    """On a smooth 3-D wave the stored non-equilibrium remainder is a small part
+    of each population, so the shifted format's error against the FP64 oracle
+    must be at most half that of the plain format (generic and row form)."""
+    for shape in ((32, 32, 32), (128, 8, 32)):
+        c = inputs.VACUUM_SPEED[model]
+        E0, B0 = inputs.gaussian_pulse(shape, 12.0, 4.0, c)
+        p = dict(eps=np.full(int(np.prod(shape)), 1.5), mu=None, sig=None, E0=E0, B0=B0)
+        o = run_oracle(model, shape, p, 100)
+        gp, _ = run_gpu(model, shape, p, 100, storage=plain, scale=scale)
+        gs, _ = run_gpu(model, shape, p, 100, storage=shifted, scale=scale)
+        for k in "EB":
+            ep, es = rel(gp[k], o[k]), rel(gs[k], o[k])
+            print(f"{model} {shape} {k}: {plain} {ep:.3e}, {shifted} {es:.3e} ({ep / es:.1f}x)", flush=True)
+            assert es < 0.5 * ep, (shape, k, ep, es)
+
+
 @pytest.mark.parametrize("model", ["mm", "hv"])
 @pytest.mark.parametrize("shape", [(12, 10, 14), (128, 6, 14)])
 def test_observations_parity(model, shape):
@@ -162,19 +203,36 @@ def test_skin_workload_parity(model):
         assert rel(g[k], o[k]) < tol, (k, rel(g[k], o[k]))
 
 
+@pytest.fixture(scope="module")
+def dipole_oracle():
+    cache = {}
+
+    def get(model):
+        if model not in cache:
+            w = inputs.dipole(model, n=256, steps=8)
+            E0, B0 = w.fields0()
+            p = dict(eps=None, mu=None, sig=w.sigma, E0=E0, B0=B0, currents=w.currents)
+            cache[model] = (w, p, run_oracle(model, w.shape, p, w.steps, probes=w.probes))
+        return cache[model]
+    return get
+
+
 @pytest.mark.parametrize("model", ["mm", "hv"])
-def test_dipole_full_size_parity(model):
+@pytest.mark.parametrize("storage,tol", [("f32", TOL), ("bf16_shifted", 1e-2)])
+def test_dipole_full_size_parity(dipole_oracle, model, storage, tol):
     """The 256^3 dipole workload (vacuum, 16-cell sponge, point current at the
-    centre) in the launch configuration the benchmark times, for 8 steps against
-    the oracle on the full lattice."""
-    w = inputs.dipole(model, n=256, steps=8)
-    E0, B0 = w.fields0()
-    p = dict(eps=None, mu=None, sig=w.sigma, E0=E0, B0=B0, currents=w.currents)
-    g, _ = run_gpu(model, w.shape, p, w.steps, probes=w.probes)
-    o = run_oracle(model, w.shape, p, w.steps, probes=w.probes)
-    for k in "EB":
-        assert rel(g[k], o[k]) < TOL, (k, rel(g[k], o[k]))
-    assert rel(g["probes"], o["probes"]) < TOL
+    centre) in the launch configuration the benchmark times (after its
+    autotuner), for 8 steps against the oracle on the full lattice."""
+    w, p, o = dipole_oracle(model)
+    lat = lbem.lattice_from_workload(w, storage=storage)
+    lat.autotune(2)
+    series = lat.set_probes(w.probes, w.steps)
+    lat.step(w.steps)
+    E, B, _, _ = lat.fields()
+    torch.cuda.synchronize()
+    g = dict(E=E.double().cpu().numpy(), B=B.double().cpu().numpy(), probes=series.cpu().numpy())
+    for k in ("E", "B", "probes"):
+        assert rel(g[k], o[k]) < tol, (k, rel(g[k], o[k]))
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
@@ -197,9 +255,10 @@ def test_dipole_light_cone_and_symmetry_long_run(model):
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
 @pytest.mark.parametrize("shape", [(10, 9, 8), (128, 4, 5)])
-def test_save_load_and_determinism(model, shape):
+@pytest.mark.parametrize("storage", ["f32", "bf16_shifted"])
+def test_save_load_and_determinism(model, shape, storage):
     p = random_problem(model, shape, seed=3)
-    lat = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"])
+    lat = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"], storage=storage)
     lat.set_fields(p["E0"], p["B0"])
     lat.set_currents(p["currents"])
     lat.step(11)
@@ -212,7 +271,7 @@ def test_save_load_and_determinism(model, shape):
     Eb = lat.fields()[0].clone()
     assert torch.equal(Ea, Eb)
     # a second lattice from scratch gives the same bits
-    lat2 = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"])
+    lat2 = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"], storage=storage)
     lat2.set_fields(p["E0"], p["B0"])
     lat2.set_currents(p["currents"])
     lat2.step(18)
@@ -262,7 +321,8 @@ def test_unstable_and_invalid_media_rejected():
         lat.set_plane_source(4, (1, 0, 0), (0, 1, 0), 10.0)
 
 
-@pytest.mark.parametrize("model,storage", [("mm", "f32"), ("mm", "bf16"), ("hv", "f32")])
+@pytest.mark.parametrize("model,storage", [("mm", "f32"), ("mm", "bf16"), ("hv", "f32"), ("mm", "bf16_shifted"),
+                                           ("hv", "f16_shifted")])
 def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage):
     """Every (address form, blocks-per-CU cap) choice of the step kernel gives
     the same bits; autotune leaves the state as it found it."""

@@ -1,9 +1,18 @@
-"""Precision sweep: the 64^3 Hertz dipole (point current at the centre, 16-cell
-sponge) for 2000 steps with populations stored in FP32, BF16 and FP16 (FP32
-collision arithmetic), against the FP64 oracle on the same lattice.  FP32 must
-stay within twice the float32 oracle's own drift (the scheme's single-precision
-floor); BF16 and FP16 must stay within their stated bounds (measured on
-MI355X: BF16 about 0.12-0.20, FP16 about 0.014-0.024 relative L2)."""
+"""Precision sweep: the 64^3 Hertz dipole (16-cell sponge) for 2000 steps with
+populations stored in FP32, BF16 and FP16, plain and equilibrium-shifted (FP32
+collision arithmetic), against the FP64 oracle on the same lattice.
+
+- Point current at the centre (the benchmark's dipole): FP32 must stay within
+  twice the float32 oracle's own drift (the scheme's single-precision floor);
+  the 16-bit formats within their stated bounds (measured on MI355X: plain
+  BF16 about 0.12-0.20, plain FP16 about 0.014-0.024 relative L2).  The
+  shifted formats may not be worse than the plain ones, but gain little here:
+  a one-cell source keeps feeding non-equilibrium content at the cell scale,
+  which the tau = 1/2 collision never damps, so the stored remainder stays
+  comparable to the population.
+- The Gaussian current profile of Section IV-C (alpha = 0.5): the fields are
+  smooth on the lattice scale and each shifted format must at least halve
+  the error of its plain counterpart (measured: 3x for MM, 8x for HV)."""
 import numpy as np
 import pytest
 import torch
@@ -15,42 +24,65 @@ pytestmark = pytest.mark.gpu
 
 STEPS = 2000
 N64 = 64
-# stated bounds after 2000 steps of the 64^3 dipole (vacuum sits on the
+# stated bounds after 2000 steps of the 64^3 point dipole (vacuum sits on the
 # stability limit, so rounding of the stored populations accumulates): BF16
 # keeps 8 significand bits, FP16 (scale 1024) 11
-BOUNDS = {"bf16": 0.3, "f16": 0.05}
+BOUNDS = {"bf16": 0.3, "f16": 0.05, "bf16_shifted": 0.3, "f16_shifted": 0.05}
+PLAIN = {"bf16_shifted": "bf16", "f16_shifted": "f16"}
 
 
 def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+def oracle_fields(w, real):
+    P = oracle.Problem(w.model, w.shape, sigma=w.sigma, currents=w.currents)
+    f = oracle.init(P, *w.fields0(), real=real)
+    oracle.run(P, f, 0, w.steps)
+    E, B, _, _ = oracle.fields(P, f, w.steps)
+    print(f"oracle {w.model} {real} done", flush=True)
+    return E, B
+
+
 @pytest.fixture(scope="module", params=["mm", "hv"])
 def reference(request):
-    model = request.param
-    w = inputs.dipole(model, n=N64, steps=STEPS)
-    P = oracle.Problem(model, w.shape, sigma=w.sigma, currents=w.currents)
-    out = {}
-    for real in ("f64", "f32"):
-        f = oracle.init(P, *w.fields0(), real=real)
-        oracle.run(P, f, 0, STEPS)
-        E, B, _, _ = oracle.fields(P, f, STEPS)
-        out[real] = (E, B)
-        print(f"oracle {model} {real} done", flush=True)
-    return model, w, out
+    w = inputs.dipole(request.param, n=N64, steps=STEPS)
+    return w, {real: oracle_fields(w, real) for real in ("f64", "f32")}, {}
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def gpu_errors(w, ref64, cache, storage):
+    if storage not in cache:
+        lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=1024.0 if "f16" in storage else 0.0)
+        lat.step(w.steps)
+        E, B, _, _ = lat.fields()
+        torch.cuda.synchronize()
+        cache[storage] = (rel(E.double().cpu().numpy(), ref64[0]), rel(B.double().cpu().numpy(), ref64[1]))
+    return cache[storage]
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "bf16_shifted", "f16_shifted"])
 def test_precision_sweep(reference, storage):
-    model, w, ref = reference
+    w, ref, cache = reference
     E64, B64 = ref["f64"]
     floor = max(rel(ref["f32"][0], E64), rel(ref["f32"][1], B64))
-    lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=1024.0 if storage == "f16" else 0.0)
-    lat.step(STEPS)
-    E, B, _, _ = lat.fields()
-    torch.cuda.synchronize()
-    eE = rel(E.double().cpu().numpy(), E64)
-    eB = rel(B.double().cpu().numpy(), B64)
-    print(f"{model} {storage}: rel L2 E {eE:.3e} B {eB:.3e} (float32 oracle floor {floor:.3e})", flush=True)
+    eE, eB = gpu_errors(w, ref["f64"], cache, storage)
+    print(f"{w.model} {storage}: rel L2 E {eE:.3e} B {eB:.3e} (float32 oracle floor {floor:.3e})", flush=True)
     bound = max(1e-5, 2 * floor) if storage == "f32" else BOUNDS[storage]
     assert eE < bound and eB < bound
+    if storage in PLAIN:
+        pE, pB = gpu_errors(w, ref["f64"], cache, PLAIN[storage])
+        print(f"{w.model} {storage}: {pE / eE:.2f}x (E) and {pB / eB:.2f}x (B) below {PLAIN[storage]}", flush=True)
+        assert eE <= 1.05 * pE and eB <= 1.05 * pB
+
+
+@pytest.mark.parametrize("model", ["mm", "hv"])
+def test_shifted_storage_gain_with_gaussian_source(model):
+    w = inputs.dipole(model, n=N64, steps=STEPS, source="gaussian")
+    ref64 = oracle_fields(w, "f64")
+    cache = {}
+    for shifted, plain in PLAIN.items():
+        eE, eB = gpu_errors(w, ref64, cache, shifted)
+        pE, pB = gpu_errors(w, ref64, cache, plain)
+        print(f"{model} gaussian source: {plain} {pE:.3e}/{pB:.3e}, {shifted} {eE:.3e}/{eB:.3e} "
+              f"({pE / eE:.1f}x, {pB / eB:.1f}x)", flush=True)
+        assert eE < 0.5 * pE and eB < 0.5 * pB
