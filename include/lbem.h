@@ -179,11 +179,18 @@ lbem_status lbem_get_fields(lbem_lattice *lat, float *E, float *B, float *D, flo
 lbem_status lbem_energy(lbem_lattice *lat, double *out);
 
 /* Launch tuning of the step kernel, per parity (index 0 even, 1 odd time
- * level): form[p] in {0, 1} selects one of two equivalent address forms of
- * the row kernel (1: store addresses formed after the collision, which lowers
- * register use), blocks_per_cu[p] caps the blocks resident per compute unit
- * (0: no cap; implemented with unused dynamic LDS).  Results are bit-identical
- * for every choice; only the speed differs.  create() sets measured defaults. */
+ * level).  form[p] = kernel + 4 * order:
+ *   kernel, for lattices whose x extent is 128, 256, 384 or 512 (one
+ *     workgroup per x-row): 0 and 1 are the row form, whose +-1 x shifts go
+ *     through LDS so that every HBM access is an aligned row, with store
+ *     addresses formed before (0) or after (1, fewer registers) the
+ *     collision; 2 addresses every neighbour directly.  Other lattices have
+ *     one kernel and ignore this part.
+ *   order 1 renumbers the workgroups so that each of the 8 XCDs (which
+ *     receive workgroups in turn) sweeps one contiguous eighth of the lattice.
+ * blocks_per_cu[p] caps the blocks resident per compute unit (0: no cap;
+ * implemented with unused dynamic LDS).  Results are bit-identical for every
+ * choice; only the speed differs.  create() sets measured defaults. */
 lbem_status lbem_set_tuning(lbem_lattice *lat, const int32_t *form, const int32_t *blocks_per_cu);
 lbem_status lbem_get_tuning(lbem_lattice *lat, int32_t *form, int32_t *blocks_per_cu);
 

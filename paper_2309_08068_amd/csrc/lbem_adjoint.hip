@@ -250,7 +250,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjArgs a) {
     using R = typename AdjCell<M>::Rev;
     float mu[M::Q];
     gather<R, ODD, StF32>(a.lam, N, nb, mu, 1.f);
-    const float E[3] = {a.E[c], a.E[N + c], a.E[2 * N + c]};
+    const float E[3] = {__builtin_nontemporal_load(a.E + c), __builtin_nontemporal_load(a.E + N + c),
+                        __builtin_nontemporal_load(a.E + 2 * N + c)};
     const CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
     float E0c[3] = {0.f, 0.f, 0.f};
     if (a.E0) {
@@ -280,7 +281,8 @@ __global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
     RowIO<R, StF32, RB> io(a.lam, N, a.ny, a.nz, row);
     float mu[M::Q];
     io.template gather<ODD>(mu, sh, 1.f);
-    const float E[3] = {a.E[c], a.E[N + c], a.E[2 * N + c]};
+    const float E[3] = {__builtin_nontemporal_load(a.E + c), __builtin_nontemporal_load(a.E + N + c),
+                        __builtin_nontemporal_load(a.E + 2 * N + c)};
     const CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
     float E0c[3] = {0.f, 0.f, 0.f};
     if (a.E0) {

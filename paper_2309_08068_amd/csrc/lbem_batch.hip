@@ -549,8 +549,8 @@ lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *thr
         if (!st) st = hip_check(hipMemcpyAsync(b->ws + b->L.pop, b->ws + b->L.backup, pb, hipMemcpyDeviceToDevice, b->stream), "restore");
         b->t = t_saved;
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (st) return st;
     st = lbem_batch_set_launch(b, bt, bg);
     if (st) return st;

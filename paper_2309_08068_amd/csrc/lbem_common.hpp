@@ -77,6 +77,18 @@ struct StF16S : StF16 {
     static constexpr bool kShift = true;
 };
 
+// ------------------------------------------------------------ launch order
+// The hardware hands consecutive workgroups of a grid to the 8 XCDs in turn
+// (workgroup b runs on XCD b mod 8), each XCD with its own L2.  Renumbering so
+// that XCD k takes the k-th contiguous eighth of the blocks keeps every XCD on
+// its own contiguous stretch of each population plane (and of the shifted
+// storage's neighbour records).  A bijection of [0, G) for any G.
+constexpr uint32_t kXCDs = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
+    const uint32_t q = G / kXCDs, r = G % kXCDs, k = b % kXCDs;
+    return k * q + (k < r ? k : r) + b / kXCDs;
+}
+
 // ------------------------------------------------------------ addressing
 // Periodic neighbours of one cell: coordinates of x-1, x, x+1 and the row
 // offsets of y-1, y, y+1 and z-1, z, z+1.

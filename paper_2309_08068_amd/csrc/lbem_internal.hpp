@@ -68,6 +68,8 @@ struct StepArgs {
     float *E_out;
     // shifted storage: the two record planes (uint4 [N] each), else null
     void *rec[2];
+    // 1: blocks take rows in XCD-contiguous order (see xcd_block)
+    uint32_t xcd_order;
 };
 
 

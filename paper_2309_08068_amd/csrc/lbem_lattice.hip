@@ -25,11 +25,15 @@ using namespace lbem;
 
 // ============================================================== kernels
 
-template <class M, int ODD, class ST>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
-    __shared__ double sm_en[4], sm_det[4];
-    const uint32_t blk = blockIdx.x;
-    const uint32_t c = blk * kBlock + threadIdx.x;
+// Generic form: one thread per cell, neighbours addressed directly, BS cells
+// per block (256, or the x extent of a lattice that also has the row form,
+// so that the per-block source, probe and partial tables are shared).
+template <class M, int ODD, class ST, int BS = kBlock>
+__global__ __launch_bounds__(BS) void step_kernel(StepArgs a) {
+    constexpr int NW = BS / 64;
+    __shared__ double sm_en[NW], sm_det[NW];
+    const uint32_t blk = a.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t c = blk * BS + threadIdx.x;
     const bool live = c < a.N;
     const uint32_t cc = live ? c : a.N - 1;
     const uint32_t nxy = a.nx * a.ny;
@@ -74,10 +78,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     }
 
     // ---- observation of the state this step collided
-    if (a.E_out && live) {
-        a.E_out[c] = o.E[0];
-        a.E_out[N + c] = o.E[1];
-        a.E_out[2 * N + c] = o.E[2];
+    if (a.E_out && live) {  // frames are read back once, much later: non-temporal
+        __builtin_nontemporal_store(o.E[0], a.E_out + c);
+        __builtin_nontemporal_store(o.E[1], a.E_out + N + c);
+        __builtin_nontemporal_store(o.E[2], a.E_out + 2 * N + c);
     }
     if (a.prb_blk) {
         const int p0 = a.prb_blk[blk], p1 = a.prb_blk[blk + 1];
@@ -92,14 +96,14 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
         const double e2 = (live && int32_t(z) == a.det_z)
                               ? double(o.E[0]) * o.E[0] + double(o.E[1]) * o.E[1] + double(o.E[2]) * o.E[2]
                               : 0.0;
-        const double s = block_sum(e2, sm_det);
+        const double s = block_sum<NW>(e2, sm_det);
         if (threadIdx.x == 0) a.det_part[blk - a.det_b0] += s;
     }
     if (a.en_part) {
         const double u = live ? 0.5 * (double(o.E[0]) * o.D[0] + double(o.E[1]) * o.D[1] + double(o.E[2]) * o.D[2] +
                                        double(o.B[0]) * o.H[0] + double(o.B[1]) * o.H[1] + double(o.B[2]) * o.H[2])
                               : 0.0;
-        const double s = block_sum(u, sm_en);
+        const double s = block_sum<NW>(u, sm_en);
         if (threadIdx.x == 0) a.en_part[blk] = s;
     }
 }
@@ -116,7 +120,7 @@ __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
     using T = typename ST::T;
     __shared__ T sh[ODD ? n_xshift<M>() : 1][RB];
     __shared__ double sm_en[NW], sm_det[NW];
-    const uint32_t row = blockIdx.x;  // y + ny z
+    const uint32_t row = a.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;  // y + ny z
     const uint32_t x = threadIdx.x;
     const uint32_t z = row / a.ny;
     const uint32_t c = row * RB + x;
@@ -152,9 +156,9 @@ __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
 
     // ---- observation of the state this step collided
     if (a.E_out) {
-        a.E_out[c] = o.E[0];
-        a.E_out[N + c] = o.E[1];
-        a.E_out[2 * N + c] = o.E[2];
+        __builtin_nontemporal_store(o.E[0], a.E_out + c);
+        __builtin_nontemporal_store(o.E[1], a.E_out + N + c);
+        __builtin_nontemporal_store(o.E[2], a.E_out + 2 * N + c);
     }
     if (a.prb_blk) {
         const int p0 = a.prb_blk[row], p1 = a.prb_blk[row + 1];
@@ -647,11 +651,16 @@ lbem_status lbem_set_energy_series(lbem_lattice *lat, int32_t every, int64_t cap
     return LBEM_OK;
 }
 
-// Kernel of the row form for a tuning choice (form = LATE) and its static LDS.
+// Kernel of a lattice with x extent RB for a tuning choice: form 0 / 1 = the
+// row form with early / late store addresses, 2 = the generic form with
+// blocks of one x-row.
 template <class M, int ODD, class ST, int RB>
 static const void *row_kernel_ptr(int form) {
-    return form ? reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1>)
-                : reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 0>);
+    switch (form) {
+        case 0: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 0>);
+        case 1: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1>);
+        default: return reinterpret_cast<const void *>(&step_kernel<M, ODD, ST, RB>);
+    }
 }
 
 template <class M, int ODD, class ST>
@@ -699,9 +708,11 @@ static size_t lds_pad_for(const void *kernel, int cap) {
 }
 
 void lbem::dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd) {
-    const void *k = step_kernel_of(lat, odd, lat->tune_form[odd]);
+    const void *k = step_kernel_of(lat, odd, lat->tune_form[odd] & 3);
     const uint32_t rb = row_block(&lat->d);
-    void *args[] = {const_cast<StepArgs *>(&a)};
+    StepArgs b = a;
+    b.xcd_order = uint32_t(lat->tune_form[odd] >> 2) & 1u;
+    void *args[] = {&b};
     (void)hipLaunchKernel(k, dim3(lat->nblocks), dim3(rb ? rb : kBlock), args, lat->tune_pad[odd], lat->stream);
 }
 
@@ -889,13 +900,14 @@ lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t) {
 lbem_status lbem_set_tuning(lbem_lattice *lat, const int32_t *form, const int32_t *blocks_per_cu) {
     if (!lat || !form || !blocks_per_cu) return fail(LBEM_EINVAL, "null argument");
     for (int p = 0; p < 2; ++p) {
-        if (form[p] != 0 && form[p] != 1) return fail(LBEM_EINVAL, "form must be 0 or 1");
+        if (form[p] < 0 || form[p] > 6 || (form[p] & 3) == 3)
+            return fail(LBEM_EINVAL, "form must be 0, 1 or 2, plus 4 for the XCD-contiguous order");
         if (blocks_per_cu[p] < 0 || blocks_per_cu[p] > 64) return fail(LBEM_EINVAL, "blocks_per_cu must be in [0, 64]");
     }
     for (int p = 0; p < 2; ++p) {
         lat->tune_form[p] = form[p];
         lat->tune_cap[p] = blocks_per_cu[p];
-        lat->tune_pad[p] = lds_pad_for(step_kernel_of(lat, p, form[p]), blocks_per_cu[p]);
+        lat->tune_pad[p] = lds_pad_for(step_kernel_of(lat, p, form[p] & 3), blocks_per_cu[p]);
     }
     return LBEM_OK;
 }
@@ -925,8 +937,11 @@ lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup) 
     const StepArgs a = base_step_args(lat);
     for (int p = 0; p < 2 && !st; ++p) {
         float best = 1e30f;
-        for (int form = 0; form < 2 && !st; ++form)
+        static const int row_forms[] = {0, 1, 2, 4, 5, 6}, generic_forms[] = {0, 4};
+        const bool rowf = row_block(&lat->d) != 0;
+        for (int fi = 0; fi < (rowf ? 6 : 2) && !st; ++fi)
             for (int cap : caps) {
+                const int form = rowf ? row_forms[fi] : generic_forms[fi];
                 int32_t f2[2] = {lat->tune_form[0], lat->tune_form[1]}, c2[2] = {lat->tune_cap[0], lat->tune_cap[1]};
                 f2[p] = form;
                 c2[p] = cap;
@@ -953,8 +968,8 @@ lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup) 
             st = lbem_set_tuning(lat, f2, c2);
         }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     lbem_status st2 = copy_state(lat, nullptr, backup, lat->t);
     return st ? st : st2;
 }

@@ -329,7 +329,7 @@ def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, stora
     shape = (128, 6, 10)
     p = random_problem(model, shape, seed=21)
     ref = None
-    for form in ((0, 0), (1, 1), (0, 1)):
+    for form in ((0, 0), (1, 1), (0, 1), (2, 2), (2, 1), (4, 5), (6, 4)):
         for cap in ((0, 0), (2, 3), (4, 2)):
             lat = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"], storage=storage)
             lat.set_fields(p["E0"], p["B0"])
