@@ -44,7 +44,8 @@ struct HVRev {
 };
 
 struct AdjArgs {
-    float *lam;  // adjoint state [Q][N], FP32, AA layout of the reversed velocities
+    float *lam;  // adjoint state, FP32, the populations' layout, AA order of the reversed velocities
+    PopLayout pl;
     const float *eps, *mu, *sig;
     const float *E;  // forward E(f_n) [3][N]
     uint32_t nx, ny, nz, N;
@@ -247,9 +248,10 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjArgs a) {
     const uint32_t z = c / nxy, rem = c - z * nxy, y = rem / a.nx, x = rem - y * a.nx;
     const Nbr nb = make_nbr(c, x, y, z, a.nx, a.ny, a.nz);
     const size_t N = a.N;
+    const size_t P = a.pl.C;  // plane stride (generic lattices are a single chunk)
     using R = typename AdjCell<M>::Rev;
     float mu[M::Q];
-    gather<R, ODD, StF32>(a.lam, N, nb, mu, 1.f);
+    gather<R, ODD, StF32>(a.lam, P, nb, mu, 1.f);
     const float E[3] = {__builtin_nontemporal_load(a.E + c), __builtin_nontemporal_load(a.E + N + c),
                         __builtin_nontemporal_load(a.E + 2 * N + c)};
     const CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjArgs a) {
     Nbr nb2 = nb;
     float *lam2 = a.lam;
     late_addresses(nb2, lam2, mu[0]);
-    scatter<R, ODD, StF32>(lam2, N, nb2, mu, 1.f);
+    scatter<R, ODD, StF32>(lam2, P, nb2, mu, 1.f);
 }
 
 // Row form of the adjoint step (one block per x-row, see RowIO).
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
     const uint32_t z = row / a.ny;
     const uint32_t c = row * RB + threadIdx.x;
     const size_t N = a.N;
-    RowIO<R, StF32, RB> io(a.lam, N, a.ny, a.nz, row);
+    RowIO<R, StF32, RB> io(a.lam, a.pl, a.ny, a.nz, row);
     float mu[M::Q];
     io.template gather<ODD>(mu, sh, 1.f);
     const float E[3] = {__builtin_nontemporal_load(a.E + c), __builtin_nontemporal_load(a.E + N + c),
@@ -326,7 +328,7 @@ AdjLayout adj_layout(const lbem_desc *d, int64_t nsteps, int32_t K, int32_t keep
     L.frames = off;
     off = al(off + size_t(L.keep) * size_t(K) * 3 * N * 4);
     L.lam = off;
-    off = al(off + N * (d->model == LBEM_MM ? 50 : 36) * 4);
+    off = al(off + size_t(pop_elems(d)) * 4);
     L.g32 = off;
     off = al(off + N * 2 * 4);
     L.total = off;
@@ -419,8 +421,9 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
     // gradients and the adjoint state start at zero
     hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(grad_eps), 2 * N);
     hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(grad_sigma), 2 * N);
-    hipLaunchKernelGGL(zero_bytes, dim3(grid256(lat->Q * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.lam),
-                       lat->Q * N);
+    const size_t lam_words = size_t(pop_elems(&lat->d));
+    hipLaunchKernelGGL(zero_bytes, dim3(grid256(lam_words)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.lam),
+                       lam_words);
     hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.g32), 2 * N);
     lbem_status st = hip_check(hipGetLastError(), "zero");
     if (st) return st;
@@ -434,6 +437,7 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
     aa.ny = lat->d.ny;
     aa.nz = lat->d.nz;
     aa.N = lat->N;
+    aa.pl = lat->pl;
     aa.det_z = lat->adj_det;
     aa.g_eps = reinterpret_cast<float *>(w + L.g32);
     aa.g_sig = aa.g_eps + N;

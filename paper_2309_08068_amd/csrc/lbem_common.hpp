@@ -43,12 +43,8 @@ struct StBF16 {
     static constexpr int kBytes = 2;
     static constexpr bool kShift = false;
     __device__ static float cvt(T r, float) { return __uint_as_float(uint32_t(r) << 16); }
-    // round to nearest, ties to even (inputs are finite)
-    __device__ static T pack(float v, float) {
-        uint32_t u = __float_as_uint(v);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return uint16_t(u >> 16);
-    }
+    // round to nearest, ties to even (one v_cvt_pk_bf16_f32 on gfx950)
+    __device__ static T pack(float v, float) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)); }
     template <bool NT = false>
     __device__ static float load(const T *p, uint32_t i, float inv) { return cvt(raw<T, NT>(p + i), inv); }
     template <bool NT = false>
@@ -88,6 +84,26 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
     const uint32_t q = G / kXCDs, r = G % kXCDs, k = b % kXCDs;
     return k * q + (k < r ? k : r) + b / kXCDs;
 }
+
+// ------------------------------------------------------------ population layout
+// Cells are grouped into chunks of 2^rshift consecutive x-rows (row = y + ny z);
+// a chunk holds all Q population planes of its cells together, so element
+// (q, row, x) lives at (row >> rshift) * QC + q * C + (row & mask) * nx + x
+// with C cells per chunk and QC = Q * C.  One step then walks a few MB of
+// address space per chunk instead of Q planes spread over the whole state,
+// which keeps the GPU's address translation within reach on large lattices.
+// A lattice with a single chunk (C = N) is the plain [Q][N] layout.
+struct PopLayout {
+    uint32_t nx, rshift, C;  // x extent, log2 of rows per chunk, cells per chunk
+    uint64_t QC;             // elements per chunk
+    __host__ __device__ uint64_t base(uint32_t row) const {
+        return uint64_t(row >> rshift) * QC + uint64_t(row & ((1u << rshift) - 1u)) * nx;
+    }
+    __host__ __device__ uint64_t index(int q, uint32_t cell) const {
+        const uint32_t row = cell / nx;
+        return base(row) + uint64_t(q) * C + (cell - row * nx);
+    }
+};
 
 // ------------------------------------------------------------ addressing
 // Periodic neighbours of one cell: coordinates of x-1, x, x+1 and the row
@@ -140,6 +156,17 @@ __device__ __forceinline__ void gather(const typename ST::T *__restrict__ pop, s
         } else {
             f[q] = ST::template load<true>(pop + size_t(q) * N, nb.c, inv_scale);
         }
+    }
+}
+
+// gather for any layout (element indices from PopLayout; used off the hot path)
+template <class M, int ODD, class ST>
+__device__ __forceinline__ void gather_any(const typename ST::T *__restrict__ pop, const PopLayout &L, const Nbr &nb,
+                                           float (&f)[M::Q], float inv_scale) {
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) {
+        if (ODD) f[q] = ST::cvt(pop[L.index(M::opp(q), nb.at(-M::vel(q, 0), -M::vel(q, 1), -M::vel(q, 2)))], inv_scale);
+        else f[q] = ST::cvt(pop[L.index(q, nb.c)], inv_scale);
     }
 }
 
@@ -204,19 +231,20 @@ constexpr int n_xshift() {
 // whole x-row of RB cells (y, z uniform).  Every HBM access is the aligned
 // row segment of one population plane, with the non-temporal hint; the +-1 x
 // shifts of the odd parity go through the LDS array sh[n_xshift][RB], which
-// keeps partial cache lines out of the memory traffic.  Addresses are a
-// uniform row base (scalar registers) plus one 32-bit byte offset of x (a
-// plane of a lattice in this form holds fewer than 2^30 cells).
+// keeps partial cache lines out of the memory traffic.  The direct variant
+// (gather_direct / scatter_direct) addresses the shifted cells in HBM instead
+// (no LDS; shared cache lines, so no non-temporal hint on those).  Addresses
+// are a uniform row base (scalar registers) plus one 32-bit byte offset of x.
 template <class M, class ST, int RB>
 struct RowIO {
     using T = typename ST::T;
     const char *pop;
-    size_t N;
+    PopLayout L;
     uint32_t ny, x, xo;
     uint32_t yr[3], zr[3];
 
-    __device__ RowIO(const void *p, size_t n, uint32_t ny_, uint32_t nz, uint32_t row)
-        : pop(static_cast<const char *>(p)), N(n), ny(ny_), x(threadIdx.x), xo(threadIdx.x * uint32_t(sizeof(T))) {
+    __device__ RowIO(const void *p, const PopLayout &l, uint32_t ny_, uint32_t nz, uint32_t row)
+        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(threadIdx.x), xo(threadIdx.x * uint32_t(sizeof(T))) {
         const uint32_t y = row % ny_, z = row / ny_;
         yr[0] = y == 0 ? ny_ - 1 : y - 1;
         yr[1] = y;
@@ -225,15 +253,24 @@ struct RowIO {
         zr[1] = z;
         zr[2] = z + 1 == nz ? 0 : z + 1;
     }
+    __device__ uint32_t row_of(int dy, int dz) const { return yr[dy + 1] + ny * zr[dz + 1]; }
+    // byte offset of (q, row + (dy, dz), x = 0)
+    __device__ uint64_t row_base(int q, int dy, int dz) const {
+        return (L.base(row_of(dy, dz)) + uint64_t(q) * L.C) * sizeof(T);
+    }
     __device__ T *at(int q, int dy, int dz) const {
-        return reinterpret_cast<T *>(const_cast<char *>(pop) +
-                                     (size_t(q) * N + size_t(yr[dy + 1] + ny * zr[dz + 1]) * RB) * sizeof(T) + xo);
+        return reinterpret_cast<T *>(const_cast<char *>(pop) + row_base(q, dy, dz) + xo);
+    }
+    // x + dx, periodic along the row
+    __device__ T *at_x(int q, int dy, int dz, int dx) const {
+        return reinterpret_cast<T *>(const_cast<char *>(pop) + row_base(q, dy, dz) +
+                                     ((x + uint32_t(RB + dx)) % uint32_t(RB)) * uint32_t(sizeof(T)));
     }
     // store addresses formed after the collision (see late_addresses)
-    __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo) : "v"(after)); }
-    // cell index of x + (dx, dy, dz), |d| <= 1, periodic
+    __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo), "+v"(x) : "v"(after)); }
+    // cell index of x + (dx, dy, dz), |d| <= 1, periodic (for per-cell arrays)
     __device__ uint32_t cell(int dx, int dy, int dz) const {
-        return (yr[dy + 1] + ny * zr[dz + 1]) * uint32_t(RB) + (x + uint32_t(RB + dx)) % uint32_t(RB);
+        return row_of(dy, dz) * uint32_t(RB) + (x + uint32_t(RB + dx)) % uint32_t(RB);
     }
 
     template <int ODD>
@@ -277,6 +314,29 @@ struct RowIO {
 #pragma unroll
             for (int q = 0; q < M::Q; ++q)
                 if (M::vel(q, 0) != 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), sh[k++][x]);
+        }
+    }
+
+    template <int ODD>
+    __device__ void gather_direct(float (&f)[M::Q], float inv_scale) const {
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q) {
+            if (!ODD) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
+            else if (M::vel(q, 0) == 0)
+                f[q] = ST::cvt(raw<T, true>(at(M::opp(q), -M::vel(q, 1), -M::vel(q, 2))), inv_scale);
+            else
+                f[q] = ST::cvt(raw<T, false>(at_x(M::opp(q), -M::vel(q, 1), -M::vel(q, 2), -M::vel(q, 0))),
+                               inv_scale);
+        }
+    }
+
+    template <int ODD>
+    __device__ void scatter_direct(const float (&f)[M::Q], float scale) const {
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q) {
+            if (!ODD) put<T, true>(at(M::opp(q), 0, 0), ST::pack(f[q], scale));
+            else if (M::vel(q, 0) == 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
+            else put<T, false>(at_x(q, M::vel(q, 1), M::vel(q, 2), M::vel(q, 0)), ST::pack(f[q], scale));
         }
     }
 };

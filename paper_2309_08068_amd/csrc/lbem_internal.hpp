@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/lbem.h"
+#include "lbem_common.hpp"
 
 namespace lbem {
 
@@ -18,12 +19,41 @@ struct WsLayout {
 
 WsLayout layout(const lbem_desc *d);
 
+// x extent handled by the row form of the step kernel (one block per x-row),
+// or 0 when the lattice uses the generic form.
+inline uint32_t row_block(const lbem_desc *d) {
+    return (d->nx == 128 || d->nx == 256 || d->nx == 384 || d->nx == 512) ? uint32_t(d->nx) : 0u;
+}
+
 // Equilibrium-shifted storage formats keep two planes of 16-byte per-cell
 // records (the step at time t reads plane (t + 1) & 1 and writes plane t & 1).
 inline bool shifted(int32_t storage) { return storage == LBEM_BF16_SHIFTED || storage == LBEM_F16_SHIFTED; }
-inline size_t pop_bytes(const lbem_desc *d) {
-    return size_t(d->nx) * d->ny * d->nz * (d->model == LBEM_MM ? 50 : 36) * (d->storage == LBEM_F32 ? 4 : 2);
+// Population layout (see PopLayout): row-form lattices use chunks of a power
+// of two of x-rows holding about kChunkCells cells; a lattice that fits in one
+// chunk, and every generic-form lattice, is a single chunk of N cells.
+constexpr uint32_t kChunkCells = 65536;
+inline PopLayout pop_layout(const lbem_desc *d) {
+    const uint32_t Q = d->model == LBEM_MM ? 50 : 36;
+    const uint64_t rows = uint64_t(d->ny) * d->nz;
+    PopLayout L{uint32_t(d->nx), 31u, uint32_t(rows * d->nx), 0};
+    if (row_block(d)) {
+        uint32_t sh = 0;
+        while ((uint64_t(2) << sh) * d->nx <= kChunkCells) ++sh;
+        if ((uint64_t(1) << sh) < rows) {
+            L.rshift = sh;
+            L.C = (1u << sh) * uint32_t(d->nx);
+        }
+    }
+    L.QC = uint64_t(Q) * L.C;
+    return L;
 }
+inline uint64_t pop_elems(const lbem_desc *d) {
+    const PopLayout L = pop_layout(d);
+    const uint64_t rows = uint64_t(d->ny) * d->nz;
+    const uint64_t nchunks = L.rshift == 31 ? 1 : (rows + (uint64_t(1) << L.rshift) - 1) >> L.rshift;
+    return nchunks * L.QC;
+}
+inline size_t pop_bytes(const lbem_desc *d) { return size_t(pop_elems(d)) * (d->storage == LBEM_F32 ? 4 : 2); }
 constexpr size_t kRecBytes = 16;
 // Bytes of one saved state: the populations, and for the shifted formats the
 // record plane the next step reads.
@@ -31,9 +61,6 @@ inline size_t state_bytes(const lbem_desc *d) {
     return pop_bytes(d) + (shifted(d->storage) ? size_t(d->nx) * d->ny * d->nz * kRecBytes : 0);
 }
 
-// x extent handled by the row form of the step kernel (one block per x-row),
-// or 0 when the lattice uses the generic form.
-uint32_t row_block(const lbem_desc *d);
 
 // Record a message for lbem_last_error and return st.
 lbem_status fail(lbem_status st, const char *fmt, ...);
@@ -45,6 +72,7 @@ double two_pi_frac(double n, double period, double phase);
 // Arguments of one launch of the 3-D step kernel.
 struct StepArgs {
     void *pop;
+    PopLayout pl;
     const float *eps, *mu, *sig;
     uint32_t nx, ny, nz, N;
     float scale, inv_scale;
@@ -88,6 +116,7 @@ struct lbem_lattice {
     char *ws;
     size_t ws_bytes;
     lbem::WsLayout L;
+    lbem::PopLayout pl;
     // sources
     int32_t nsrc;
     double src_period, src_phase;

@@ -25,25 +25,25 @@ using namespace lbem;
 
 // ============================================================== kernels
 
-// Generic form: one thread per cell, neighbours addressed directly, BS cells
-// per block (256, or the x extent of a lattice that also has the row form,
-// so that the per-block source, probe and partial tables are shared).
-template <class M, int ODD, class ST, int BS = kBlock>
-__global__ __launch_bounds__(BS) void step_kernel(StepArgs a) {
-    constexpr int NW = BS / 64;
+// Generic form: one thread per cell, neighbours addressed directly, blocks of
+// 256 cells (any lattice shape; such lattices are a single layout chunk).
+template <class M, int ODD, class ST>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
+    constexpr int NW = kBlock / 64;
     __shared__ double sm_en[NW], sm_det[NW];
     const uint32_t blk = a.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    const uint32_t c = blk * BS + threadIdx.x;
+    const uint32_t c = blk * kBlock + threadIdx.x;
     const bool live = c < a.N;
     const uint32_t cc = live ? c : a.N - 1;
     const uint32_t nxy = a.nx * a.ny;
     const uint32_t z = cc / nxy, rem = cc - z * nxy, y = rem / a.nx, x = rem - y * a.nx;
     const Nbr nb = make_nbr(cc, x, y, z, a.nx, a.ny, a.nz);
     const size_t N = a.N;
+    const size_t P = a.pl.C;  // population plane stride: generic lattices are a single chunk
     auto *pop = static_cast<typename ST::T *>(a.pop);
 
     float f[M::Q];
-    if (live) gather<M, ODD, ST>(pop, N, nb, f, a.inv_scale);
+    if (live) gather<M, ODD, ST>(pop, P, nb, f, a.inv_scale);
     else
         for (int q = 0; q < M::Q; ++q) f[q] = 0.f;
     if constexpr (ST::kShift)
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(BS) void step_kernel(StepArgs a) {
         Nbr nb2 = nb;
         auto *pop2 = pop;
         late_addresses(nb2, pop2, f[0]);
-        scatter<M, ODD, ST>(pop2, N, nb2, f, a.scale);
+        scatter<M, ODD, ST>(pop2, P, nb2, f, a.scale);
     }
 
     // ---- observation of the state this step collided
@@ -112,22 +112,24 @@ __global__ __launch_bounds__(BS) void step_kernel(StepArgs a) {
 // threads = one full x-row; y and z are uniform per block), see RowIO.  Same
 // arithmetic as step_kernel, bit for bit.
 // LATE = 1 forms the store addresses after the collision (see late_addresses);
-// which form is faster depends on model, storage and parity, so both exist
+// DIRECT = 1 addresses the x-shifted cells in HBM instead of through LDS.
+// Which variant is faster depends on model, storage and parity, so all exist
 // and the launch tuning picks one.
-template <class M, int ODD, class ST, int RB, int LATE>
+template <class M, int ODD, class ST, int RB, int LATE, int DIRECT>
 __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
     constexpr int NW = RB / 64;
     using T = typename ST::T;
-    __shared__ T sh[ODD ? n_xshift<M>() : 1][RB];
+    __shared__ T sh[(ODD && !DIRECT) ? n_xshift<M>() : 1][RB];
     __shared__ double sm_en[NW], sm_det[NW];
     const uint32_t row = a.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;  // y + ny z
     const uint32_t x = threadIdx.x;
     const uint32_t z = row / a.ny;
     const uint32_t c = row * RB + x;
     const size_t N = a.N;
-    RowIO<M, ST, RB> io(a.pop, N, a.ny, a.nz, row);
+    RowIO<M, ST, RB> io(a.pop, a.pl, a.ny, a.nz, row);
     float f[M::Q];
-    io.template gather<ODD>(f, sh, a.inv_scale);
+    if (DIRECT) io.template gather_direct<ODD>(f, a.inv_scale);
+    else io.template gather<ODD>(f, sh, a.inv_scale);
     if constexpr (ST::kShift)
         unshift<M>(f, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]),
                    [&](int dx, int dy, int dz) { return io.cell(dx, dy, dz); });
@@ -152,7 +154,8 @@ __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
                      static_cast<u32x4 *>(a.rec[ODD ? 1 : 0]), c, true);
 
     if (LATE) io.late(f[0]);
-    io.template scatter<ODD>(f, sh, a.scale);
+    if (DIRECT) io.template scatter_direct<ODD>(f, a.scale);
+    else io.template scatter<ODD>(f, sh, a.scale);
 
     // ---- observation of the state this step collided
     if (a.E_out) {
@@ -186,6 +189,7 @@ __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
 
 struct ObsArgs {
     const void *pop;
+    PopLayout pl;
     const float *eps, *mu, *sig;
     uint32_t nx, ny, nz, N;
     uint32_t bu;  // cells per source-table unit
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
     const Nbr nb = make_nbr(cc, x, y, z, a.nx, a.ny, a.nz);
     const size_t N = a.N;
     float f[M::Q];
-    gather<M, ODD, ST>(static_cast<const typename ST::T *>(a.pop), N, nb, f, a.inv_scale);
+    gather_any<M, ODD, ST>(static_cast<const typename ST::T *>(a.pop), a.pl, nb, f, a.inv_scale);
     if constexpr (ST::kShift)
         unshift<M>(f, static_cast<const u32x4 *>(a.rec), [&](int dx, int dy, int dz) { return nb.at(dx, dy, dz); });
     CellMedia m{a.eps[cc], a.mu[cc], a.sig[cc]};
@@ -249,9 +253,9 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
 // holds f_q - phi_q(R_{c - v_q}) with the records of the same fields, which
 // init_record_kernel has written to the plane the first step reads.
 template <class M, class ST>
-__global__ __launch_bounds__(kBlock) void init_kernel(void *pop, const float *eps, const float *mu, const float *E,
-                                                      const float *B, uint32_t nx, uint32_t ny, uint32_t nz,
-                                                      uint32_t N, float scale, const void *rec) {
+__global__ __launch_bounds__(kBlock) void init_kernel(void *pop, PopLayout pl, const float *eps, const float *mu,
+                                                      const float *E, const float *B, uint32_t nx, uint32_t ny,
+                                                      uint32_t nz, uint32_t N, float scale, const void *rec) {
     const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= N) return;
     CellMedia m{eps[c], mu[c], 0.f};
@@ -269,8 +273,9 @@ __global__ __launch_bounds__(kBlock) void init_kernel(void *pop, const float *ep
         for (int q = 0; q < M::Q; ++q) f[q] -= g[q];
     }
     auto *p = static_cast<typename ST::T *>(pop);
+    const uint64_t i0 = pl.index(0, c);
 #pragma unroll
-    for (int q = 0; q < M::Q; ++q) ST::store(p + size_t(q) * N, c, f[q], scale);
+    for (int q = 0; q < M::Q; ++q) ST::store(p + i0 + uint64_t(q) * pl.C, 0, f[q], scale);
 }
 
 __global__ __launch_bounds__(kBlock) void init_record_kernel(void *rec, const float *eps, const float *mu,
@@ -331,10 +336,6 @@ size_t storage_bytes(int st) { return st == LBEM_F32 ? 4 : 2; }
 }  // namespace
 
 namespace lbem {
-uint32_t row_block(const lbem_desc *d) {
-    return (d->nx == 128 || d->nx == 256 || d->nx == 384 || d->nx == 512) ? uint32_t(d->nx) : 0u;
-}
-
 WsLayout layout(const lbem_desc *d) {
     WsLayout L;
     const size_t N = size_t(d->nx) * d->ny * d->nz;
@@ -348,7 +349,7 @@ WsLayout layout(const lbem_desc *d) {
         off = align256(off + bytes);
         return o;
     };
-    L.pop = take(N * model_q(d->model) * storage_bytes(d->storage));
+    L.pop = take(pop_bytes(d));
     L.rec = take(shifted(d->storage) ? 2 * N * kRecBytes : 0);
     L.eps = take(N * 4);
     L.mu = take(N * 4);
@@ -417,6 +418,7 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     lat->ws = static_cast<char *>(workspace);
     lat->ws_bytes = workspace_bytes;
     lat->L = L;
+    lat->pl = pop_layout(desc);
     lat->plane_z = -1;
     lat->det_z = -1;
     lat->t = 0;
@@ -485,9 +487,9 @@ static void launch_init(lbem_lattice *lat, const float *E, const float *B) {
     char *rec = ST::kShift ? read_rec(lat, 0) : nullptr;
     if (ST::kShift)
         hipLaunchKernelGGL(init_record_kernel, dim3(lat->nobs), dim3(kBlock), 0, lat->stream, rec, eps, mu, E, B, lat->N);
-    hipLaunchKernelGGL((init_kernel<M, ST>), dim3(lat->nobs), dim3(kBlock), 0, lat->stream, lat->ws + lat->L.pop, eps,
-                       mu, E, B, uint32_t(lat->d.nx), uint32_t(lat->d.ny), uint32_t(lat->d.nz), lat->N, lat->scale,
-                       rec);
+    hipLaunchKernelGGL((init_kernel<M, ST>), dim3(lat->nobs), dim3(kBlock), 0, lat->stream, lat->ws + lat->L.pop,
+                       lat->pl, eps, mu, E, B, uint32_t(lat->d.nx), uint32_t(lat->d.ny), uint32_t(lat->d.nz), lat->N,
+                       lat->scale, rec);
 }
 
 template <class M>
@@ -652,14 +654,14 @@ lbem_status lbem_set_energy_series(lbem_lattice *lat, int32_t every, int64_t cap
 }
 
 // Kernel of a lattice with x extent RB for a tuning choice: form 0 / 1 = the
-// row form with early / late store addresses, 2 = the generic form with
-// blocks of one x-row.
+// row form with LDS x-shifts and early / late store addresses, 2 = the row
+// form with direct x-shifted addressing (late addresses).
 template <class M, int ODD, class ST, int RB>
 static const void *row_kernel_ptr(int form) {
     switch (form) {
-        case 0: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 0>);
-        case 1: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1>);
-        default: return reinterpret_cast<const void *>(&step_kernel<M, ODD, ST, RB>);
+        case 0: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 0, 0>);
+        case 1: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1, 0>);
+        default: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1, 1>);
     }
 }
 
@@ -728,6 +730,7 @@ StepArgs lbem::base_step_args(lbem_lattice *lat) {
     const WsLayout &L = lat->L;
     StepArgs a{};
     a.pop = lat->ws + L.pop;
+    a.pl = lat->pl;
     a.eps = reinterpret_cast<const float *>(lat->ws + L.eps);
     a.mu = reinterpret_cast<const float *>(lat->ws + L.mu);
     a.sig = reinterpret_cast<const float *>(lat->ws + L.sig);
@@ -823,6 +826,7 @@ static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, floa
     const WsLayout &L = lat->L;
     ObsArgs a{};
     a.pop = lat->ws + L.pop;
+    a.pl = lat->pl;
     a.eps = reinterpret_cast<const float *>(lat->ws + L.eps);
     a.mu = reinterpret_cast<const float *>(lat->ws + L.mu);
     a.sig = reinterpret_cast<const float *>(lat->ws + L.sig);

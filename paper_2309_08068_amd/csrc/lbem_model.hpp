@@ -323,42 +323,40 @@ struct Rec {
 };
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t bf16_rn(float v) {
-    uint32_t u = __float_as_uint(v);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
+// Two floats rounded to BF16 (nearest, ties to even) in one 32-bit word, low
+// half first: one v_cvt_pk_bf16_f32 on gfx950.
+__device__ __forceinline__ uint32_t bf16x2_rn(float lo, float hi) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const f2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, b2));
 }
-__device__ __forceinline__ float bf16_f(uint32_t h) { return __uint_as_float(h << 16); }
-
-// Round a record to BF16; returns the packed 16 bytes and the rounded values.
-__device__ __forceinline__ u32x4 rec_pack(const float E[3], const float B[3], float eps, float imu, Rec &r) {
-    const uint16_t h[8] = {bf16_rn(E[0]), bf16_rn(E[1]), bf16_rn(E[2]), bf16_rn(B[0]),
-                           bf16_rn(B[1]), bf16_rn(B[2]), bf16_rn(eps), bf16_rn(imu)};
-    for (int a = 0; a < 3; ++a) {
-        r.E[a] = bf16_f(h[a]);
-        r.B[a] = bf16_f(h[3 + a]);
-    }
-    r.eps = bf16_f(h[6]);
-    r.imu = bf16_f(h[7]);
-    u32x4 u;
-    u.x = uint32_t(h[0]) | uint32_t(h[1]) << 16;
-    u.y = uint32_t(h[2]) | uint32_t(h[3]) << 16;
-    u.z = uint32_t(h[4]) | uint32_t(h[5]) << 16;
-    u.w = uint32_t(h[6]) | uint32_t(h[7]) << 16;
-    return u;
-}
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 __device__ __forceinline__ Rec rec_unpack(u32x4 u) {
     Rec r;
-    r.E[0] = bf16_f(u.x & 0xffffu);
-    r.E[1] = bf16_f(u.x >> 16);
-    r.E[2] = bf16_f(u.y & 0xffffu);
-    r.B[0] = bf16_f(u.y >> 16);
-    r.B[1] = bf16_f(u.z & 0xffffu);
-    r.B[2] = bf16_f(u.z >> 16);
-    r.eps = bf16_f(u.w & 0xffffu);
-    r.imu = bf16_f(u.w >> 16);
+    r.E[0] = bf16_lo(u.x);
+    r.E[1] = bf16_hi(u.x);
+    r.E[2] = bf16_lo(u.y);
+    r.B[0] = bf16_hi(u.y);
+    r.B[1] = bf16_lo(u.z);
+    r.B[2] = bf16_hi(u.z);
+    r.eps = bf16_lo(u.w);
+    r.imu = bf16_hi(u.w);
     return r;
+}
+
+// Round a record to BF16; returns the packed 16 bytes and (in r) the rounded
+// values, exactly as rec_unpack will read them back.
+__device__ __forceinline__ u32x4 rec_pack(const float E[3], const float B[3], float eps, float imu, Rec &r) {
+    u32x4 u;
+    u.x = bf16x2_rn(E[0], E[1]);
+    u.y = bf16x2_rn(E[2], B[0]);
+    u.z = bf16x2_rn(B[1], B[2]);
+    u.w = bf16x2_rn(eps, imu);
+    r = rec_unpack(u);
+    return u;
 }
 
 // Per model: the distinct moving velocities k (every shifted population

@@ -2,6 +2,8 @@
 function include/lbem.h declares, and rejects bad arguments before touching
 the device."""
 import ctypes as C
+
+import numpy as np
 import os
 import re
 
@@ -76,6 +78,21 @@ def test_shifted_storage_sizes(lib, storage, q):
     out = C.c_size_t()
     d = lbem.desc("mm", (16, 16, 16), storage)
     assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0 and out.value == n * q * 2 + 16 * n
+
+
+@pytest.mark.parametrize("shape,chunks,chunk_cells", [((256, 20, 13), 2, 65536), ((384, 10, 13), 2, 49152),
+                                                      ((512, 3, 45), 2, 65536), ((128, 9, 60), 2, 65536),
+                                                      ((256, 16, 16), 1, 65536), ((100, 30, 40), 1, 120000)])
+def test_population_layout_chunks(lib, shape, chunks, chunk_cells):
+    """Row-form lattices store populations in chunks of a power of two of
+    x-rows (about 64 Ki cells); the last chunk is padded.  A lattice that fits
+    in one chunk, and any generic-form lattice, is one chunk of N cells."""
+    out = C.c_size_t()
+    d = lbem.desc("mm", shape, "f32")
+    assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0
+    n = int(np.prod(shape))
+    expect = chunks * 50 * chunk_cells * 4 if chunks > 1 else 50 * n * 4
+    assert out.value == expect
 
 
 def test_batch_rejects_shifted_storage(lib):

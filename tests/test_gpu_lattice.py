@@ -75,9 +75,12 @@ def run_oracle(model, shape, p, steps, real="f64", probes=None, det_z=None, ener
 
 
 # generic form (odd sizes, ragged last block, axes of length 1) and the row form
-# (x extent 128, 256, 384 or 512: one block per x-row, LDS x-shifts)
+# (x extent 128, 256, 384 or 512: one block per x-row, LDS x-shifts), in one
+# layout chunk and -- the last four, with more x-rows than a chunk holds
+# (512, 256, 128 and 128 rows) -- across chunks with a partial last chunk
 SHAPES = [(1, 1, 17), (7, 5, 9), (16, 16, 16), (33, 3, 5), (300, 1, 1), (1, 40, 1), (9, 1, 31),
-          (128, 3, 5), (256, 2, 3), (384, 1, 2), (512, 2, 1)]
+          (128, 3, 5), (256, 2, 3), (384, 1, 2), (512, 2, 1),
+          (128, 9, 60), (256, 20, 13), (384, 10, 13), (512, 3, 45)]
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
@@ -137,7 +140,7 @@ def test_shifted_storage_beats_plain_on_smooth_fields(model, plain, shifted, sca
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
-@pytest.mark.parametrize("shape", [(12, 10, 14), (128, 6, 14)])
+@pytest.mark.parametrize("shape", [(12, 10, 14), (128, 6, 14), (128, 9, 60)])
 def test_observations_parity(model, shape):
     """Probe series, energy series and detector-plane accumulation (FP64 on both
     sides), in the generic and the row form of the step kernel."""
@@ -254,7 +257,7 @@ def test_dipole_light_cone_and_symmetry_long_run(model):
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
-@pytest.mark.parametrize("shape", [(10, 9, 8), (128, 4, 5)])
+@pytest.mark.parametrize("shape", [(10, 9, 8), (128, 4, 5), (256, 20, 13)])
 @pytest.mark.parametrize("storage", ["f32", "bf16_shifted"])
 def test_save_load_and_determinism(model, shape, storage):
     p = random_problem(model, shape, seed=3)
@@ -326,7 +329,7 @@ def test_unstable_and_invalid_media_rejected():
 def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage):
     """Every (address form, blocks-per-CU cap) choice of the step kernel gives
     the same bits; autotune leaves the state as it found it."""
-    shape = (128, 6, 10)
+    shape = (256, 20, 13)  # two layout chunks
     p = random_problem(model, shape, seed=21)
     ref = None
     for form in ((0, 0), (1, 1), (0, 1), (2, 2), (2, 1), (4, 5), (6, 4)):
