@@ -89,10 +89,10 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
 // Cells are grouped into chunks of 2^rshift consecutive x-rows (row = y + ny z);
 // a chunk holds all Q population planes of its cells together, so element
 // (q, row, x) lives at (row >> rshift) * QC + q * C + (row & mask) * nx + x
-// with C cells per chunk and QC = Q * C.  One step then walks a few MB of
-// address space per chunk instead of Q planes spread over the whole state,
-// which keeps the GPU's address translation within reach on large lattices.
-// A lattice with a single chunk (C = N) is the plain [Q][N] layout.
+// with C cells per chunk and QC = Q * C.  A workgroup's Q streams then lie
+// within about a megabyte instead of Q planes spread over the whole state,
+// which keeps address translation and DRAM pages local.  A lattice with a
+// single chunk (C = N) is the plain [Q][N] layout.
 struct PopLayout {
     uint32_t nx, rshift, C;  // x extent, log2 of rows per chunk, cells per chunk
     uint64_t QC;             // elements per chunk

@@ -80,19 +80,21 @@ def test_shifted_storage_sizes(lib, storage, q):
     assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0 and out.value == n * q * 2 + 16 * n
 
 
-@pytest.mark.parametrize("shape,chunks,chunk_cells", [((256, 20, 13), 2, 65536), ((384, 10, 13), 2, 49152),
-                                                      ((512, 3, 45), 2, 65536), ((128, 9, 60), 2, 65536),
-                                                      ((256, 16, 16), 1, 65536), ((100, 30, 40), 1, 120000)])
-def test_population_layout_chunks(lib, shape, chunks, chunk_cells):
+@pytest.mark.parametrize("shape,storage,chunks,chunk_cells", [
+    ((256, 20, 13), "f32", 9, 8192), ((384, 10, 13), "f32", 9, 6144), ((512, 3, 45), "f32", 9, 8192),
+    ((128, 9, 60), "f32", 9, 8192), ((256, 16, 16), "f32", 8, 8192), ((256, 20, 13), "bf16", 5, 16384),
+    ((128, 8, 8), "f32", 1, 0), ((100, 30, 40), "f32", 1, 0)])
+def test_population_layout_chunks(lib, shape, storage, chunks, chunk_cells):
     """Row-form lattices store populations in chunks of a power of two of
-    x-rows (about 64 Ki cells); the last chunk is padded.  A lattice that fits
-    in one chunk, and any generic-form lattice, is one chunk of N cells."""
+    x-rows with at most 32 KB per population plane; the last chunk is padded.
+    A lattice that fits in one chunk, and any generic-form lattice, is one
+    chunk of N cells."""
     out = C.c_size_t()
-    d = lbem.desc("mm", shape, "f32")
+    d = lbem.desc("mm", shape, storage)
     assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0
+    s = 4 if storage == "f32" else 2
     n = int(np.prod(shape))
-    expect = chunks * 50 * chunk_cells * 4 if chunks > 1 else 50 * n * 4
-    assert out.value == expect
+    assert out.value == (chunks * 50 * chunk_cells * s if chunk_cells else 50 * n * s)
 
 
 def test_batch_rejects_shifted_storage(lib):
