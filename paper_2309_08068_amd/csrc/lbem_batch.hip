@@ -30,6 +30,7 @@ constexpr int kMaxGroups = 4096;
 
 struct BatchArgs {
     void *pop;
+    PopLayout pl;  // chunks of cells (a "row" is one cell here)
     const float *eps, *mu, *sig;
     const int32_t *inst_off;  // [n + 1]
     const int32_t *wg_start;  // [G + 1] ranges into items
@@ -39,20 +40,24 @@ struct BatchArgs {
     int32_t parity;  // time level parity at the first step
 };
 
-// One cell of a 1-D instance occupying global cells [s, s + L).
+// One cell of a 1-D instance occupying global cells [s, s + L).  Populations
+// are in chunks of cells (PopLayout with rows of one cell): element (q, g) is
+// base(g) + q * C, so a workgroup's instance spans one or two chunks.
 template <class M, int ODD, class ST>
-__device__ __forceinline__ void cell_1d(typename ST::T *__restrict__ pop, size_t total, const float *eps,
+__device__ __forceinline__ void cell_1d(typename ST::T *__restrict__ pop, const PopLayout &pl, const float *eps,
                                         const float *mu, const float *sig, uint32_t s, uint32_t L, uint32_t i,
                                         CellFields *out) {
     const uint32_t g = s + i;
     const uint32_t gm = s + (i == 0 ? L - 1 : i - 1);
     const uint32_t gp = s + (i + 1 == L ? 0 : i + 1);
+    const uint64_t b = pl.base(g), bm = pl.base(gm), bp = pl.base(gp);
+    const uint64_t C = pl.C;
     float f[M::Q];
 #pragma unroll
     for (int q = 0; q < M::Q; ++q) {
         const int vz = M::vel(q, 2);
-        if (ODD) f[q] = ST::load(pop + size_t(M::opp(q)) * total, vz > 0 ? gm : (vz < 0 ? gp : g), 1.f);
-        else f[q] = ST::load(pop + size_t(q) * total, g, 1.f);
+        if (ODD) f[q] = ST::cvt(pop[uint64_t(M::opp(q)) * C + (vz > 0 ? bm : (vz < 0 ? bp : b))], 1.f);
+        else f[q] = ST::cvt(pop[uint64_t(q) * C + b], 1.f);
     }
     const CellMedia m{eps[g], mu[g], sig[g]};
     const float Js[3] = {0.f, 0.f, 0.f};
@@ -63,14 +68,14 @@ __device__ __forceinline__ void cell_1d(typename ST::T *__restrict__ pop, size_t
         return;
     }
     // store addresses formed after the collision (see late_addresses)
-    uint32_t g2 = g, gm2 = gm, gp2 = gp;
+    uint64_t b2 = b, bm2 = bm, bp2 = bp;
     typename ST::T *pop2 = pop;
-    asm volatile("" : "+v"(g2), "+v"(gm2), "+v"(gp2), "+s"(pop2) : "v"(f[0]));
+    asm volatile("" : "+v"(b2), "+v"(bm2), "+v"(bp2), "+s"(pop2) : "v"(f[0]));
 #pragma unroll
     for (int q = 0; q < M::Q; ++q) {
         const int vz = M::vel(q, 2);
-        if (ODD) ST::store(pop2 + size_t(q) * total, vz > 0 ? gp2 : (vz < 0 ? gm2 : g2), f[q], 1.f);
-        else ST::store(pop2 + size_t(M::opp(q)) * total, g2, f[q], 1.f);
+        if (ODD) pop2[uint64_t(q) * C + (vz > 0 ? bp2 : (vz < 0 ? bm2 : b2))] = ST::pack(f[q], 1.f);
+        else pop2[uint64_t(M::opp(q)) * C + b2] = ST::pack(f[q], 1.f);
     }
 }
 
@@ -85,10 +90,10 @@ __global__ __launch_bounds__(T) void batch_persistent(BatchArgs a) {
         for (int64_t k = 0; k < a.nsteps; ++k) {
             if (((a.parity + k) & 1) == 0) {
                 for (uint32_t i = threadIdx.x; i < L; i += T)
-                    cell_1d<M, 0, ST>(pop, a.total, a.eps, a.mu, a.sig, s, L, i, nullptr);
+                    cell_1d<M, 0, ST>(pop, a.pl, a.eps, a.mu, a.sig, s, L, i, nullptr);
             } else {
                 for (uint32_t i = threadIdx.x; i < L; i += T)
-                    cell_1d<M, 1, ST>(pop, a.total, a.eps, a.mu, a.sig, s, L, i, nullptr);
+                    cell_1d<M, 1, ST>(pop, a.pl, a.eps, a.mu, a.sig, s, L, i, nullptr);
             }
             __syncthreads();  // the next step reads what neighbouring threads wrote
         }
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(T) void batch_persistent(BatchArgs a) {
 template <class M, int ODD, class ST>
 __global__ __launch_bounds__(kBlock) void batch_one(BatchArgs a, uint32_t s, uint32_t L) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < L) cell_1d<M, ODD, ST>(static_cast<typename ST::T *>(a.pop), a.total, a.eps, a.mu, a.sig, s, L, i, nullptr);
+    if (i < L) cell_1d<M, ODD, ST>(static_cast<typename ST::T *>(a.pop), a.pl, a.eps, a.mu, a.sig, s, L, i, nullptr);
 }
 
 template <class M, int ODD, class ST>
@@ -110,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void batch_fields(BatchArgs a, const int32_
     const uint32_t s = uint32_t(a.inst_off[b]);
     const uint32_t L = uint32_t(a.inst_off[b + 1]) - s;
     CellFields o;
-    cell_1d<M, ODD, ST>(static_cast<typename ST::T *>(a.pop), a.total, a.eps, a.mu, a.sig, s, L, g - s, &o);
+    cell_1d<M, ODD, ST>(static_cast<typename ST::T *>(a.pop), a.pl, a.eps, a.mu, a.sig, s, L, g - s, &o);
     for (int d = 0; d < 3; ++d) {
         if (E) E[d * a.total + g] = o.E[d];
         if (B) B[d * a.total + g] = o.B[d];
@@ -118,8 +123,8 @@ __global__ __launch_bounds__(kBlock) void batch_fields(BatchArgs a, const int32_
 }
 
 template <class M, class ST>
-__global__ __launch_bounds__(kBlock) void batch_init(void *pop, const float *eps, const float *mu, const float *E,
-                                                     const float *B, uint32_t total) {
+__global__ __launch_bounds__(kBlock) void batch_init(void *pop, PopLayout pl, const float *eps, const float *mu,
+                                                     const float *E, const float *B, uint32_t total) {
     const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= total) return;
     const CellMedia m{eps[c], mu[c], 0.f};
@@ -127,9 +132,9 @@ __global__ __launch_bounds__(kBlock) void batch_init(void *pop, const float *eps
     const float b[3] = {B[c], B[size_t(total) + c], B[2 * size_t(total) + c]};
     float f[M::Q];
     Cell<M>::equilibrium(f, m, e, b);
-    auto *p = static_cast<typename ST::T *>(pop);
+    auto *p = static_cast<typename ST::T *>(pop) + pl.base(c);
 #pragma unroll
-    for (int q = 0; q < M::Q; ++q) ST::store(p + size_t(q) * total, c, f[q], 1.f);
+    for (int q = 0; q < M::Q; ++q) p[uint64_t(q) * pl.C] = ST::pack(f[q], 1.f);
 }
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -137,6 +142,22 @@ size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 struct BatchLayout {
     size_t pop, backup, eps, mu, sig, inst_off, cell_inst, wg_start, items, flags, total;
 };
+
+// Chunks of cells with at most kChunkBytes per population plane (as for the
+// 3-D lattice; a row of the layout is one cell); one chunk if all cells fit.
+PopLayout batch_pop_layout(int model, int storage, size_t total) {
+    const uint32_t Q = model == LBEM_MM ? 50 : 36;
+    const uint32_t cells = kChunkBytes / (storage == LBEM_F32 ? 4u : 2u);
+    PopLayout pl{1u, 31u, uint32_t(total), 0};
+    if (total > cells) {
+        uint32_t sh = 0;
+        while ((2u << sh) <= cells) ++sh;
+        pl.rshift = sh;
+        pl.C = 1u << sh;
+    }
+    pl.QC = uint64_t(Q) * pl.C;
+    return pl;
+}
 
 BatchLayout batch_layout(int model, int storage, int32_t n, size_t total) {
     BatchLayout L{};
@@ -146,7 +167,9 @@ BatchLayout batch_layout(int model, int storage, int32_t n, size_t total) {
         off = al(off + bytes);
         return o;
     };
-    const size_t pb = total * (model == LBEM_MM ? 50 : 36) * (storage == LBEM_F32 ? 4 : 2);
+    const PopLayout pl = batch_pop_layout(model, storage, total);
+    const size_t nchunks = pl.rshift == 31 ? 1 : (total + pl.C - 1) / pl.C;
+    const size_t pb = nchunks * pl.QC * (storage == LBEM_F32 ? 4 : 2);
     L.pop = take(pb);
     L.backup = take(pb);
     L.eps = take(total * 4);
@@ -184,6 +207,7 @@ struct lbem_batch {
     hipStream_t stream;
     char *ws;
     BatchLayout L;
+    PopLayout pl;
     int ncu;
     int threads, gpc, groups;
     int64_t t;
@@ -205,6 +229,7 @@ T *at(lbem_batch *b, size_t off) {
 BatchArgs args_of(lbem_batch *b, int64_t nsteps) {
     BatchArgs a{};
     a.pop = b->ws + b->L.pop;
+    a.pl = b->pl;
     a.eps = at<const float>(b, b->L.eps);
     a.mu = at<const float>(b, b->L.mu);
     a.sig = at<const float>(b, b->L.sig);
@@ -348,6 +373,7 @@ lbem_status lbem_batch_create(int32_t model, int32_t storage, int32_t n, const i
     b->stream = static_cast<hipStream_t>(stream);
     b->ws = static_cast<char *>(workspace);
     b->L = L;
+    b->pl = batch_pop_layout(model, storage, total);
     b->ncu = ncu > 0 ? ncu : 1;
     b->threads = 256;
     b->gpc = 2;
@@ -399,9 +425,9 @@ static void batch_init_m(lbem_batch *b, const float *E, const float *B) {
     void *pop = b->ws + b->L.pop;
     const float *eps = at<const float>(b, b->L.eps), *mu = at<const float>(b, b->L.mu);
     switch (b->storage) {
-        case LBEM_F32: hipLaunchKernelGGL((batch_init<M, StF32>), dim3(g), dim3(kBlock), 0, b->stream, pop, eps, mu, E, B, b->total); break;
-        case LBEM_BF16: hipLaunchKernelGGL((batch_init<M, StBF16>), dim3(g), dim3(kBlock), 0, b->stream, pop, eps, mu, E, B, b->total); break;
-        default: hipLaunchKernelGGL((batch_init<M, StF16>), dim3(g), dim3(kBlock), 0, b->stream, pop, eps, mu, E, B, b->total); break;
+        case LBEM_F32: hipLaunchKernelGGL((batch_init<M, StF32>), dim3(g), dim3(kBlock), 0, b->stream, pop, b->pl, eps, mu, E, B, b->total); break;
+        case LBEM_BF16: hipLaunchKernelGGL((batch_init<M, StBF16>), dim3(g), dim3(kBlock), 0, b->stream, pop, b->pl, eps, mu, E, B, b->total); break;
+        default: hipLaunchKernelGGL((batch_init<M, StF16>), dim3(g), dim3(kBlock), 0, b->stream, pop, b->pl, eps, mu, E, B, b->total); break;
     }
 }
 
