@@ -242,7 +242,10 @@ lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, i
  * dL/deps_r and dL/dsigma (dev double [N]) times `scale`.  If E0 and B0 (dev
  * float [3][N]) are given, the state at t0 is taken to be f_eq(E0, B0) of the
  * current media (lbem_set_fields), and its dependence on eps_r is included.
- * Leaves the lattice state as the forward left it. */
+ * Leaves the lattice state as the forward left it.  The first call on a
+ * lattice also times the adjoint kernel's launch variants on the workspace
+ * (as lbem_autotune does for the step kernel; synchronises the stream once)
+ * and keeps the fastest for later calls. */
 lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, const float *E0, const float *B0,
                                   double scale, double *grad_eps, double *grad_sigma);
 

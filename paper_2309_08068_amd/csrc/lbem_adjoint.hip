@@ -271,18 +271,20 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjArgs a) {
     scatter<R, ODD, StF32>(lam2, P, nb2, mu, 1.f);
 }
 
-// Row form of the adjoint step (one block per x-row, see RowIO).
-template <class M, int ODD, int RB>
+// Row form of the adjoint step (one block per x-row, see RowIO); LATE and
+// DIRECT as for the forward row kernel.
+template <class M, int ODD, int RB, int LATE, int DIRECT>
 __global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
     using R = typename AdjCell<M>::Rev;
-    __shared__ float sh[ODD ? n_xshift<R>() : 1][RB];
+    __shared__ float sh[(ODD && !DIRECT) ? n_xshift<R>() : 1][RB];
     const uint32_t row = blockIdx.x;
     const uint32_t z = row / a.ny;
     const uint32_t c = row * RB + threadIdx.x;
     const size_t N = a.N;
     RowIO<R, StF32, RB> io(a.lam, a.pl, a.ny, a.nz, row);
     float mu[M::Q];
-    io.template gather<ODD>(mu, sh, 1.f);
+    if (DIRECT) io.template gather_direct<ODD>(mu, 1.f);
+    else io.template gather<ODD>(mu, sh, 1.f);
     const float E[3] = {__builtin_nontemporal_load(a.E + c), __builtin_nontemporal_load(a.E + N + c),
                         __builtin_nontemporal_load(a.E + 2 * N + c)};
     const CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
@@ -296,8 +298,9 @@ __global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
     AdjCell<M>::step(mu, E, m, int32_t(z) == a.det_z, a.E0 != nullptr, E0c, gE, gS);
     a.g_eps[c] += gE;
     a.g_sig[c] += gS;
-    io.late(mu[0]);
-    io.template scatter<ODD>(mu, sh, 1.f);
+    if (LATE) io.late(mu[0]);
+    if (DIRECT) io.template scatter_direct<ODD>(mu, 1.f);
+    else io.template scatter<ODD>(mu, sh, 1.f);
 }
 
 // g64 += scale * g32 and g32 = 0 (end of a segment; FP64 across segments)
@@ -337,21 +340,78 @@ AdjLayout adj_layout(const lbem_desc *d, int64_t nsteps, int32_t K, int32_t keep
 
 uint32_t grid256(size_t n) { return uint32_t((n + kBlock - 1) / kBlock); }
 
-template <class M, int ODD>
-void launch_adjoint_p(const AdjArgs &aa, uint32_t rb, uint32_t rows, uint32_t g256, hipStream_t s) {
-    switch (rb) {
-        case 128: hipLaunchKernelGGL((adjoint_row_kernel<M, ODD, 128>), dim3(rows), dim3(128), 0, s, aa); break;
-        case 256: hipLaunchKernelGGL((adjoint_row_kernel<M, ODD, 256>), dim3(rows), dim3(256), 0, s, aa); break;
-        case 384: hipLaunchKernelGGL((adjoint_row_kernel<M, ODD, 384>), dim3(rows), dim3(384), 0, s, aa); break;
-        case 512: hipLaunchKernelGGL((adjoint_row_kernel<M, ODD, 512>), dim3(rows), dim3(512), 0, s, aa); break;
-        default: hipLaunchKernelGGL((adjoint_kernel<M, ODD>), dim3(g256), dim3(kBlock), 0, s, aa); break;
+template <class M, int ODD, int RB>
+const void *adjoint_row_ptr(int form) {
+    switch (form) {
+        case 0: return reinterpret_cast<const void *>(&adjoint_row_kernel<M, ODD, RB, 0, 0>);
+        case 1: return reinterpret_cast<const void *>(&adjoint_row_kernel<M, ODD, RB, 1, 0>);
+        default: return reinterpret_cast<const void *>(&adjoint_row_kernel<M, ODD, RB, 1, 1>);
     }
 }
 
-template <class M>
-void launch_adjoint(const AdjArgs &aa, int odd, uint32_t rb, uint32_t rows, uint32_t g256, hipStream_t s) {
-    if (odd) launch_adjoint_p<M, 1>(aa, rb, rows, g256, s);
-    else launch_adjoint_p<M, 0>(aa, rb, rows, g256, s);
+template <class M, int ODD>
+const void *adjoint_ptr_p(uint32_t rb, int form) {
+    switch (rb) {
+        case 128: return adjoint_row_ptr<M, ODD, 128>(form);
+        case 256: return adjoint_row_ptr<M, ODD, 256>(form);
+        case 384: return adjoint_row_ptr<M, ODD, 384>(form);
+        case 512: return adjoint_row_ptr<M, ODD, 512>(form);
+        default: return reinterpret_cast<const void *>(&adjoint_kernel<M, ODD>);
+    }
+}
+
+const void *adjoint_ptr(const lbem_lattice *lat, int odd, int form) {
+    const uint32_t rb = row_block(&lat->d);
+    if (lat->d.model == LBEM_MM) return odd ? adjoint_ptr_p<MM, 1>(rb, form) : adjoint_ptr_p<MM, 0>(rb, form);
+    return odd ? adjoint_ptr_p<HV, 1>(rb, form) : adjoint_ptr_p<HV, 0>(rb, form);
+}
+
+void launch_adjoint(const lbem_lattice *lat, const AdjArgs &aa, int odd, int form, size_t pad) {
+    const uint32_t rb = row_block(&lat->d);
+    void *args[] = {const_cast<AdjArgs *>(&aa)};
+    (void)hipLaunchKernel(adjoint_ptr(lat, odd, form), dim3(rb ? lat->nblocks : grid256(lat->N)),
+                          dim3(rb ? rb : kBlock), args, pad, lat->stream);
+}
+
+// Choose the adjoint row kernel's form and occupancy cap per parity by timing
+// a few launches on the workspace (whose adjoint state and accumulators the
+// caller clears afterwards).
+lbem_status tune_adjoint(lbem_lattice *lat, const AdjArgs &aa) {
+    lat->adj_tuned = 1;
+    for (int p = 0; p < 2; ++p) {
+        lat->adj_form[p] = 1;
+        lat->adj_cap[p] = 0;
+        lat->adj_pad[p] = 0;
+    }
+    if (!row_block(&lat->d)) return LBEM_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    lbem_status st = hip_check(hipEventCreate(&e0), "event");
+    if (!st) st = hip_check(hipEventCreate(&e1), "event");
+    static const int caps[] = {0, 2, 3, 4};
+    for (int p = 0; p < 2 && !st; ++p) {
+        float best = 1e30f;
+        for (int form = 0; form < 3 && !st; ++form)
+            for (int cap : caps) {
+                const size_t pad = lds_pad_for(adjoint_ptr(lat, p, form), cap);
+                launch_adjoint(lat, aa, p, form, pad);  // warm-up
+                st = hip_check(hipEventRecord(e0, lat->stream), "record");
+                for (int k = 0; k < 3 && !st; ++k) launch_adjoint(lat, aa, p, form, pad);
+                if (!st) st = hip_check(hipGetLastError(), "trial launch");
+                if (!st) st = hip_check(hipEventRecord(e1, lat->stream), "record");
+                if (!st) st = hip_check(hipEventSynchronize(e1), "sync");
+                float ms = 0.f;
+                if (!st) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+                if (!st && ms < best) {
+                    best = ms;
+                    lat->adj_form[p] = form;
+                    lat->adj_cap[p] = cap;
+                    lat->adj_pad[p] = pad;
+                }
+            }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return st;
 }
 
 }  // namespace
@@ -418,15 +478,6 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
     const size_t sb = (L.state_bytes + 255) & ~size_t(255);
     const size_t N = lat->N;
     hipStream_t s = lat->stream;
-    // gradients and the adjoint state start at zero
-    hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(grad_eps), 2 * N);
-    hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(grad_sigma), 2 * N);
-    const size_t lam_words = size_t(pop_elems(&lat->d));
-    hipLaunchKernelGGL(zero_bytes, dim3(grid256(lam_words)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.lam),
-                       lam_words);
-    hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.g32), 2 * N);
-    lbem_status st = hip_check(hipGetLastError(), "zero");
-    if (st) return st;
     float *frames = reinterpret_cast<float *>(w + L.frames);
     AdjArgs aa{};
     aa.lam = reinterpret_cast<float *>(w + L.lam);
@@ -441,7 +492,20 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
     aa.det_z = lat->adj_det;
     aa.g_eps = reinterpret_cast<float *>(w + L.g32);
     aa.g_sig = aa.g_eps + N;
-    const uint32_t rb = row_block(&lat->d);
+    if (!lat->adj_tuned) {
+        aa.E = frames;  // any frame: the trial launches only need valid memory
+        lbem_status st = tune_adjoint(lat, aa);
+        if (st) return st;
+    }
+    // gradients and the adjoint state start at zero
+    hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(grad_eps), 2 * N);
+    hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(grad_sigma), 2 * N);
+    const size_t lam_words = size_t(pop_elems(&lat->d));
+    hipLaunchKernelGGL(zero_bytes, dim3(grid256(lam_words)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.lam),
+                       lam_words);
+    hipLaunchKernelGGL(zero_bytes, dim3(grid256(2 * N)), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(w + L.g32), 2 * N);
+    lbem_status st = hip_check(hipGetLastError(), "zero");
+    if (st) return st;
     int64_t j = 0;  // adjoint steps done (parity of the adjoint AA layout)
     for (int64_t seg = L.S - 1; seg >= 0; --seg) {
         const int64_t tseg = t0 + seg * K;
@@ -468,8 +532,7 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
             aa.E0 = first ? E0 : nullptr;
             aa.B0 = first ? B0 : nullptr;
             const int odd = int(j & 1);
-            if (lat->d.model == LBEM_MM) launch_adjoint<MM>(aa, odd, rb, lat->nblocks, grid256(N), s);
-            else launch_adjoint<HV>(aa, odd, rb, lat->nblocks, grid256(N), s);
+            launch_adjoint(lat, aa, odd, lat->adj_form[odd], lat->adj_pad[odd]);
             st = hip_check(hipGetLastError(), "adjoint launch");
             if (st) return st;
             ++j;

@@ -146,6 +146,11 @@ struct lbem_lattice {
     void *adj_ws;
     int64_t adj_t0, adj_nsteps;
     int32_t adj_K, adj_keep, adj_det;
+    // launch tuning of the adjoint row kernel per parity (chosen on the first
+    // reverse pass): form (0 LDS, early addresses; 1 LDS, late; 2 direct),
+    // blocks-per-CU cap and its dynamic LDS
+    int32_t adj_tuned, adj_form[2], adj_cap[2];
+    size_t adj_pad[2];
 };
 
 
@@ -153,6 +158,9 @@ namespace lbem {
 // Step-kernel arguments for the lattice's current configuration (no
 // observation or frame output set).
 StepArgs base_step_args(lbem_lattice *lat);
+// Dynamic LDS that caps the resident blocks of `kernel` per compute unit at
+// cap (0: no cap), given its static LDS.
+size_t lds_pad_for(const void *kernel, int cap);
 // Launch one step kernel of the lattice's model and storage.
 void dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd);
 // lbem_step with every observation; if frames is set, E of the state collided

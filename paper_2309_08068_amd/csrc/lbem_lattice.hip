@@ -695,7 +695,7 @@ static const void *step_kernel_of(const lbem_lattice *lat, int odd, int form) {
 
 // Dynamic LDS that caps the resident blocks per compute unit at `cap`
 // (0: no cap), given the kernel's static LDS.
-static size_t lds_pad_for(const void *kernel, int cap) {
+size_t lbem::lds_pad_for(const void *kernel, int cap) {
     if (cap <= 0) return 0;
     hipFuncAttributes attr{};
     if (hipFuncGetAttributes(&attr, kernel) != hipSuccess) return 0;
