@@ -256,6 +256,64 @@ def test_dipole_light_cone_and_symmetry_long_run(model):
     assert d <= 1e-4 * ez.abs().max().item()
 
 
+@pytest.fixture(scope="module")
+def dipole384_f32():
+    cache = {}
+
+    def get(model, steps):
+        if (model, steps) not in cache:
+            w = inputs.dipole(model, n=384, steps=steps)
+            lat = lbem.lattice_from_workload(w)
+            lat.autotune(2)
+            lat.step(steps)
+            E, B, _, _ = lat.fields()
+            cache[(model, steps)] = (E.reshape(3, 384, 384, 384).clone(), B.reshape(3, 384, 384, 384).clone())
+            del lat
+        return cache[(model, steps)]
+    return get
+
+
+# bound on the relative L2 distance from the FP32-storage run after 150 steps
+DIPOLE384_BOUND = {"f32": 0.0, "bf16": 0.1, "f16": 0.02, "bf16_shifted": 0.1, "f16_shifted": 0.02}
+
+
+@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "bf16_shifted", "f16_shifted"])
+def test_dipole_384_properties(dipole384_f32, model, storage):
+    """The 384^3 dipole of the precision sweep, at full size in the benchmark's
+    launch configuration (autotuned), 150 steps, with properties that hold at
+    any size: fields finite; every cell outside the light cone of the source
+    (|x - c|_inf > steps: populations move at most one cell per axis per step)
+    exactly zero; the x <-> y mirror symmetry of a z-directed point source at
+    the centre; and, for the 16-bit formats, the stated bound on the distance
+    from the FP32-storage run.  The FP64 oracle at this size would hold 45 GB."""
+    steps, n, c = 150, 384, 192
+    w = inputs.dipole(model, n=n, steps=steps)
+    lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=1024.0 if "f16" in storage else 0.0)
+    lat.autotune(2)
+    lat.step(steps)
+    E, B, _, _ = lat.fields()
+    E = E.reshape(3, n, n, n)
+    B = B.reshape(3, n, n, n)
+    assert torch.isfinite(E).all() and torch.isfinite(B).all()
+    lo, hi = c - steps, c + steps
+    inside = torch.zeros((n, n, n), dtype=torch.bool, device=E.device)
+    inside[lo:hi + 1, lo:hi + 1, lo:hi + 1] = True
+    assert (E[:, ~inside] == 0).all() and (B[:, ~inside] == 0).all()
+    ez = E[2]
+    asym = ((ez - ez.transpose(1, 2)).abs().max() / ez.abs().max()).item()
+    E32, B32 = dipole384_f32(model, steps)
+    dE = ((E - E32).norm() / E32.norm()).item()
+    dB = ((B - B32).norm() / B32.norm()).item()
+    print(f"{model} {storage} 384^3: asymmetry {asym:.2e}, distance from FP32 storage E {dE:.2e} B {dB:.2e}",
+          flush=True)
+    assert asym <= (1e-4 if storage == "f32" else 2e-2)
+    if storage == "f32":
+        assert dE == 0.0 and dB == 0.0  # every launch choice gives the same bits
+    else:
+        assert dE < DIPOLE384_BOUND[storage] and dB < DIPOLE384_BOUND[storage]
+
+
 @pytest.mark.parametrize("model", ["mm", "hv"])
 @pytest.mark.parametrize("shape", [(10, 9, 8), (128, 4, 5), (256, 20, 13)])
 @pytest.mark.parametrize("storage", ["f32", "bf16_shifted"])
