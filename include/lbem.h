@@ -98,7 +98,12 @@ const char *lbem_last_error(void);
 lbem_status lbem_workspace_size(const lbem_desc *desc, size_t *bytes);
 
 /* Bytes of one population state (what save_state writes): the populations,
- * and for the shifted formats also the record plane the next step reads. */
+ * and for the shifted formats also the record plane the next step reads.  The
+ * state is an opaque byte image: populations are stored in chunks of x-rows
+ * (lattices with nx = 128, 256, 384 or 512 and more rows than one chunk
+ * holds, at most 32 KB per population plane per chunk, the last chunk padded),
+ * otherwise as [Q][N]; a state is only meaningful to a lattice with the same
+ * descriptor. */
 lbem_status lbem_state_size(const lbem_desc *desc, size_t *bytes);
 
 /* Create a lattice.
@@ -201,7 +206,8 @@ lbem_status lbem_get_tuning(lbem_lattice *lat, int32_t *form, int32_t *blocks_pe
 lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup);
 
 /* Copy the population state to dst (dev, lbem_state_size bytes) / restore it
- * together with the time level it was saved at (get it with lbem_get_time). */
+ * together with the time level it was saved at (get it with lbem_get_time).
+ * Both are asynchronous device-to-device copies on the lattice's stream. */
 lbem_status lbem_save_state(lbem_lattice *lat, void *dst);
 lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t);
 
