@@ -189,7 +189,8 @@ lbem_status lbem_energy(lbem_lattice *lat, double *out);
  *     workgroup per x-row): 0 and 1 are the row form, whose +-1 x shifts go
  *     through LDS so that every HBM access is an aligned row, with store
  *     addresses formed before (0) or after (1, fewer registers) the
- *     collision; 2 addresses every neighbour directly.  Other lattices have
+ *     collision; 2 addresses every neighbour directly; 3 does the same with
+ *     each row split into workgroups of 128 threads.  Other lattices have
  *     one kernel and ignore this part.
  *   order 1 renumbers the workgroups so that each of the 8 XCDs (which
  *     receive workgroups in turn) sweeps one contiguous eighth of the lattice.

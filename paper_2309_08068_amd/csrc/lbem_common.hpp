@@ -10,6 +10,10 @@
 namespace lbem {
 
 constexpr int kBlock = 256;  // threads per block of the lattice kernels (4 waves)
+// Per-block detector partials are kept at a stride of kSegMax slots per table
+// unit, so that a row may be split into up to kSegMax workgroups.
+constexpr int kSegMax = 4;
+constexpr int kSegThreads = 128;  // threads per workgroup of a split row
 
 // ------------------------------------------------------------ storage formats
 // Populations live in HBM as FP32, BF16 or FP16; collision math is FP32.
@@ -243,8 +247,11 @@ struct RowIO {
     uint32_t ny, x, xo;
     uint32_t yr[3], zr[3];
 
-    __device__ RowIO(const void *p, const PopLayout &l, uint32_t ny_, uint32_t nz, uint32_t row)
-        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(threadIdx.x), xo(threadIdx.x * uint32_t(sizeof(T))) {
+    // x: this thread's cell along the row (threadIdx.x unless a row is split
+    // over several workgroups)
+    __device__ RowIO(const void *p, const PopLayout &l, uint32_t ny_, uint32_t nz, uint32_t row,
+                     uint32_t x_ = threadIdx.x)
+        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_), xo(x_ * uint32_t(sizeof(T))) {
         const uint32_t y = row % ny_, z = row / ny_;
         yr[0] = y == 0 ? ny_ - 1 : y - 1;
         yr[1] = y;

@@ -161,6 +161,9 @@ StepArgs base_step_args(lbem_lattice *lat);
 // Dynamic LDS that caps the resident blocks of `kernel` per compute unit at
 // cap (0: no cap), given its static LDS.
 size_t lds_pad_for(const void *kernel, int cap);
+// Workgroups per x-row of the step kernel chosen for this parity (1 unless
+// the row is split, tuning form 3).
+uint32_t step_segments(const lbem_lattice *lat, int odd);
 // Launch one step kernel of the lattice's model and storage.
 void dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd);
 // lbem_step with every observation; if frames is set, E of the state collided

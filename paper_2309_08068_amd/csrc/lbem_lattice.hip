@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
                               ? double(o.E[0]) * o.E[0] + double(o.E[1]) * o.E[1] + double(o.E[2]) * o.E[2]
                               : 0.0;
         const double s = block_sum<NW>(e2, sm_det);
-        if (threadIdx.x == 0) a.det_part[blk - a.det_b0] += s;
+        if (threadIdx.x == 0) a.det_part[(blk - a.det_b0) * kSegMax] += s;
     }
     if (a.en_part) {
         const double u = live ? 0.5 * (double(o.E[0]) * o.D[0] + double(o.E[1]) * o.D[1] + double(o.E[2]) * o.D[2] +
@@ -108,25 +108,27 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     }
 }
 
-// Row form of the step for lattices whose x extent equals the block (RB
-// threads = one full x-row; y and z are uniform per block), see RowIO.  Same
+// Row form of the step for lattices with x extent RB: TB threads per block,
+// RB / TB blocks per x-row (y and z are uniform per block), see RowIO.  Same
 // arithmetic as step_kernel, bit for bit.
 // LATE = 1 forms the store addresses after the collision (see late_addresses);
-// DIRECT = 1 addresses the x-shifted cells in HBM instead of through LDS.
-// Which variant is faster depends on model, storage and parity, so all exist
-// and the launch tuning picks one.
-template <class M, int ODD, class ST, int RB, int LATE, int DIRECT>
-__global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
-    constexpr int NW = RB / 64;
+// DIRECT = 1 addresses the x-shifted cells in HBM instead of through LDS (a
+// split row, TB < RB, needs it).  Which variant is faster depends on model,
+// storage, parity and row length, so all exist and the launch tuning picks one.
+template <class M, int ODD, class ST, int RB, int LATE, int DIRECT, int TB = RB>
+__global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
+    static_assert(RB % TB == 0 && (TB == RB || DIRECT), "a split row needs direct addressing");
+    constexpr int NW = TB / 64, SEG = RB / TB;
     using T = typename ST::T;
     __shared__ T sh[(ODD && !DIRECT) ? n_xshift<M>() : 1][RB];
     __shared__ double sm_en[NW], sm_det[NW];
-    const uint32_t row = a.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;  // y + ny z
-    const uint32_t x = threadIdx.x;
+    const uint32_t blk = a.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t row = blk / SEG, seg = blk % SEG;  // row = y + ny z
+    const uint32_t x = seg * TB + threadIdx.x;
     const uint32_t z = row / a.ny;
     const uint32_t c = row * RB + x;
     const size_t N = a.N;
-    RowIO<M, ST, RB> io(a.pop, a.pl, a.ny, a.nz, row);
+    RowIO<M, ST, RB> io(a.pop, a.pl, a.ny, a.nz, row, x);
     float f[M::Q];
     if (DIRECT) io.template gather_direct<ODD>(f, a.inv_scale);
     else io.template gather<ODD>(f, sh, a.inv_scale);
@@ -177,13 +179,13 @@ __global__ __launch_bounds__(RB) void row_step_kernel(StepArgs a) {
                               ? double(o.E[0]) * o.E[0] + double(o.E[1]) * o.E[1] + double(o.E[2]) * o.E[2]
                               : 0.0;
         const double s = block_sum<NW>(e2, sm_det);
-        if (threadIdx.x == 0) a.det_part[row - a.det_b0] += s;
+        if (threadIdx.x == 0) a.det_part[(row - a.det_b0) * kSegMax + seg] += s;
     }
     if (a.en_part) {
         const double u = 0.5 * (double(o.E[0]) * o.D[0] + double(o.E[1]) * o.D[1] + double(o.E[2]) * o.D[2] +
                                 double(o.B[0]) * o.H[0] + double(o.B[1]) * o.H[1] + double(o.B[2]) * o.H[2]);
         const double s = block_sum<NW>(u, sm_en);
-        if (threadIdx.x == 0) a.en_part[row] = s;
+        if (threadIdx.x == 0) a.en_part[row * SEG + seg] = s;
     }
 }
 
@@ -354,9 +356,9 @@ WsLayout layout(const lbem_desc *d) {
     L.eps = take(N * 4);
     L.mu = take(N * 4);
     L.sig = take(N * 4);
-    L.en_part = take(std::max(nblocks, nobs) * 8);
+    L.en_part = take(std::max(nblocks * kSegMax, nobs) * 8);
     L.det_cap = nxy / bu + 2;
-    L.det_part = take(L.det_cap * 8);
+    L.det_part = take(L.det_cap * kSegMax * 8);
     L.src_blk = take((nblocks + 1) * 4);
     L.src_cell = take(size_t(LBEM_MAX_SOURCES) * 4);
     L.src_J0 = take(size_t(LBEM_MAX_SOURCES) * 12);
@@ -625,7 +627,7 @@ lbem_status lbem_set_detector(lbem_lattice *lat, int32_t z) {
     lat->det_z = z;
     lat->det_b0 = uint32_t((uint64_t(z) * nxy) / lat->bu);
     lat->det_b1 = uint32_t((uint64_t(z + 1) * nxy - 1) / lat->bu);
-    const size_t words = size_t(lat->L.det_cap) * 2;
+    const size_t words = size_t(lat->L.det_cap) * kSegMax * 2;
     hipLaunchKernelGGL(zero_bytes, dim3(grid_for(words)), dim3(kBlock), 0, lat->stream,
                        reinterpret_cast<uint32_t *>(lat->ws + lat->L.det_part), words);
     return hip_check(hipGetLastError(), "zero detector");
@@ -635,7 +637,8 @@ lbem_status lbem_detector_read(lbem_lattice *lat, double *out) {
     if (!lat || !out) return fail(LBEM_EINVAL, "null argument");
     if (lat->det_z < 0) return fail(LBEM_ESTATE, "no detector plane set");
     hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream,
-                       reinterpret_cast<const double *>(lat->ws + lat->L.det_part), lat->det_b1 - lat->det_b0 + 1, out);
+                       reinterpret_cast<const double *>(lat->ws + lat->L.det_part),
+                       (lat->det_b1 - lat->det_b0 + 1) * kSegMax, out);
     return hip_check(hipGetLastError(), "detector sum");
 }
 
@@ -655,13 +658,18 @@ lbem_status lbem_set_energy_series(lbem_lattice *lat, int32_t every, int64_t cap
 
 // Kernel of a lattice with x extent RB for a tuning choice: form 0 / 1 = the
 // row form with LDS x-shifts and early / late store addresses, 2 = the row
-// form with direct x-shifted addressing (late addresses).
+// form with direct x-shifted addressing (late addresses), 3 = the same with
+// each row split into workgroups of kSegThreads threads.
 template <class M, int ODD, class ST, int RB>
 static const void *row_kernel_ptr(int form) {
     switch (form) {
         case 0: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 0, 0>);
         case 1: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1, 0>);
-        default: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1, 1>);
+        case 2: return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1, 1>);
+        default:
+            if constexpr (RB > kSegThreads)
+                return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1, 1, kSegThreads>);
+            else return reinterpret_cast<const void *>(&row_step_kernel<M, ODD, ST, RB, 1, 1>);
     }
 }
 
@@ -709,13 +717,19 @@ size_t lbem::lds_pad_for(const void *kernel, int cap) {
     return std::min<size_t>(need, 65536 - attr.sharedSizeBytes);
 }
 
+uint32_t lbem::step_segments(const lbem_lattice *lat, int odd) {
+    const uint32_t rb = row_block(&lat->d);
+    return ((lat->tune_form[odd] & 3) == 3 && rb > uint32_t(kSegThreads)) ? rb / kSegThreads : 1u;
+}
+
 void lbem::dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd) {
     const void *k = step_kernel_of(lat, odd, lat->tune_form[odd] & 3);
-    const uint32_t rb = row_block(&lat->d);
+    const uint32_t rb = row_block(&lat->d), seg = step_segments(lat, odd);
     StepArgs b = a;
     b.xcd_order = uint32_t(lat->tune_form[odd] >> 2) & 1u;
     void *args[] = {&b};
-    (void)hipLaunchKernel(k, dim3(lat->nblocks), dim3(rb ? rb : kBlock), args, lat->tune_pad[odd], lat->stream);
+    (void)hipLaunchKernel(k, dim3(lat->nblocks * seg), dim3(rb ? rb / seg : kBlock), args, lat->tune_pad[odd],
+                          lat->stream);
 }
 
 namespace lbem {
@@ -792,7 +806,8 @@ lbem_status lbem::step_impl(lbem_lattice *lat, int64_t nsteps, float *frames) {
         dispatch_step(lat, a, int(t & 1));
         if (en) {
             double *dst = lat->en_series + ((t - lat->en_t0) / lat->en_every) % lat->en_cap;
-            hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream, en_part, lat->nblocks, dst);
+            hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream, en_part,
+                               lat->nblocks * step_segments(lat, int(t & 1)), dst);
         }
         lbem_status st = hip_check(hipGetLastError(), "step launch");
         if (st) return st;
@@ -904,8 +919,8 @@ lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t) {
 lbem_status lbem_set_tuning(lbem_lattice *lat, const int32_t *form, const int32_t *blocks_per_cu) {
     if (!lat || !form || !blocks_per_cu) return fail(LBEM_EINVAL, "null argument");
     for (int p = 0; p < 2; ++p) {
-        if (form[p] < 0 || form[p] > 6 || (form[p] & 3) == 3)
-            return fail(LBEM_EINVAL, "form must be 0, 1 or 2, plus 4 for the XCD-contiguous order");
+        if (form[p] < 0 || form[p] > 7)
+            return fail(LBEM_EINVAL, "form must be 0, 1, 2 or 3, plus 4 for the XCD-contiguous order");
         if (blocks_per_cu[p] < 0 || blocks_per_cu[p] > 64) return fail(LBEM_EINVAL, "blocks_per_cu must be in [0, 64]");
     }
     for (int p = 0; p < 2; ++p) {
@@ -941,11 +956,16 @@ lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup) 
     const StepArgs a = base_step_args(lat);
     for (int p = 0; p < 2 && !st; ++p) {
         float best = 1e30f;
-        static const int row_forms[] = {0, 1, 2, 4, 5, 6}, generic_forms[] = {0, 4};
-        const bool rowf = row_block(&lat->d) != 0;
-        for (int fi = 0; fi < (rowf ? 6 : 2) && !st; ++fi)
+        // candidate forms: kernels 0-2 (row lattices), 3 (rows longer than a
+        // split workgroup), each in both block orders; generic lattices: order only
+        const uint32_t rb = row_block(&lat->d);
+        int forms[8], nforms = 0;
+        for (int order = 0; order < 2; ++order)
+            for (int k = 0; k < 4; ++k)
+                if ((rb && (k < 3 || rb > uint32_t(kSegThreads))) || (!rb && k == 0)) forms[nforms++] = k + 4 * order;
+        for (int fi = 0; fi < nforms && !st; ++fi)
             for (int cap : caps) {
-                const int form = rowf ? row_forms[fi] : generic_forms[fi];
+                const int form = forms[fi];
                 int32_t f2[2] = {lat->tune_form[0], lat->tune_form[1]}, c2[2] = {lat->tune_cap[0], lat->tune_cap[1]};
                 f2[p] = form;
                 c2[p] = cap;

@@ -39,8 +39,10 @@ def random_problem(model, shape, seed, n_src=3, plane=False):
     return dict(eps=eps, mu=mu, sig=sig, E0=E0, B0=B0, currents=currents, plane=pl)
 
 
-def run_gpu(model, shape, p, steps, storage="f32", scale=0.0, probes=None, det_z=None, energy_every=0):
+def run_gpu(model, shape, p, steps, storage="f32", scale=0.0, probes=None, det_z=None, energy_every=0, tuning=None):
     lat = lbem.Lattice(model, shape, p["eps"], p.get("mu"), p.get("sig"), storage=storage, storage_scale=scale)
+    if tuning:
+        lat.set_tuning(*tuning)
     lat.set_fields(p["E0"], p["B0"])
     if p.get("currents"):
         lat.set_currents(p["currents"])
@@ -140,15 +142,17 @@ def test_shifted_storage_beats_plain_on_smooth_fields(model, plain, shifted, sca
 
 
 @pytest.mark.parametrize("model", ["mm", "hv"])
-@pytest.mark.parametrize("shape", [(12, 10, 14), (128, 6, 14), (128, 9, 60)])
-def test_observations_parity(model, shape):
+@pytest.mark.parametrize("shape,tuning", [((12, 10, 14), None), ((128, 6, 14), None), ((128, 9, 60), None),
+                                          ((384, 3, 14), ((3, 7), (0, 2))), ((256, 4, 14), ((2, 3), (2, 0)))])
+def test_observations_parity(model, shape, tuning):
     """Probe series, energy series and detector-plane accumulation (FP64 on both
-    sides), in the generic and the row form of the step kernel."""
+    sides), in the generic and the row form of the step kernel, including rows
+    split over several workgroups (tuning form 3) for one or both parities."""
     steps = 30
     p = random_problem(model, shape, seed=5)
     n = int(np.prod(shape))
     probes = [0, 17, shape[0] * shape[1] * 7 + 5, n - 1]
-    g, _ = run_gpu(model, shape, p, steps, probes=probes, det_z=6, energy_every=4)
+    g, _ = run_gpu(model, shape, p, steps, probes=probes, det_z=6, energy_every=4, tuning=tuning)
     o = run_oracle(model, shape, p, steps, probes=probes, det_z=6, energy_every=4)
     assert rel(g["probes"], o["probes"]) < TOL
     np.testing.assert_allclose(g["energy"], o["energy"], rtol=TOL)
@@ -390,7 +394,7 @@ def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, stora
     shape = (256, 20, 13)  # two layout chunks
     p = random_problem(model, shape, seed=21)
     ref = None
-    for form in ((0, 0), (1, 1), (0, 1), (2, 2), (2, 1), (4, 5), (6, 4)):
+    for form in ((0, 0), (1, 1), (0, 1), (2, 2), (2, 1), (4, 5), (6, 4), (3, 3), (7, 1)):
         for cap in ((0, 0), (2, 3), (4, 2)):
             lat = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"], storage=storage)
             lat.set_fields(p["E0"], p["B0"])
