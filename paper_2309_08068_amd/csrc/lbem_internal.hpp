@@ -30,9 +30,9 @@ inline uint32_t row_block(const lbem_desc *d) {
 inline bool shifted(int32_t storage) { return storage == LBEM_BF16_SHIFTED || storage == LBEM_F16_SHIFTED; }
 // Population layout (see PopLayout): row-form lattices use chunks of a power
 // of two of x-rows with at most kChunkBytes per population plane (measured on
-// MI355X: 32 KB beat 8 KB to 1 MB chunks and the plain [Q][N] layout, by up
-// to 15 % on large lattices); a lattice that fits in one chunk, and every
-// generic-form lattice, is a single chunk of N cells.
+// MI355X: 32 KB beat 16 KB, 64 KB and larger chunks and the plain [Q][N]
+// layout, which was up to 15 % slower on large lattices); a lattice that fits
+// in one chunk, and every generic-form lattice, is a single chunk of N cells.
 constexpr uint32_t kChunkBytes = 32768;
 inline PopLayout pop_layout(const lbem_desc *d) {
     const uint32_t Q = d->model == LBEM_MM ? 50 : 36;

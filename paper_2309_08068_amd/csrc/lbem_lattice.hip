@@ -4,8 +4,10 @@
 // cell: gather the populations (in-place AA streaming), collide (Section II or
 // III), impose hard sources, scatter, and -- when requested for this step --
 // record probes, the detector-plane |E|^2 and per-block energy partials in
-// FP64.  One thread owns one cell; cells are numbered x fastest so every
-// population plane is read and written in contiguous 256-cell runs.
+// FP64.  One thread owns one cell; cells are numbered x fastest, and a
+// workgroup owns one x-row (or a 128-cell piece of one) whose population
+// planes are contiguous runs of the layout chunk the row lies in (PopLayout),
+// or, in the generic form, a run of 256 cells of the [Q][N] layout.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
