@@ -193,7 +193,8 @@ lbem_status lbem_energy(lbem_lattice *lat, double *out);
  *     each row split into workgroups of 128 threads.  Other lattices have
  *     one kernel and ignore this part.
  *   order 1 renumbers the workgroups so that each of the 8 XCDs (which
- *     receive workgroups in turn) sweeps one contiguous eighth of the lattice.
+ *     receive workgroups in turn) takes groups of consecutive x-rows (one
+ *     layout chunk, at least 16 rows), keeping neighbouring rows on one L2.
  * blocks_per_cu[p] caps the blocks resident per compute unit (0: no cap;
  * implemented with unused dynamic LDS).  Results are bit-identical for every
  * choice; only the speed differs.  create() sets measured defaults. */

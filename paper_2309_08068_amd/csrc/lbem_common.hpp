@@ -79,14 +79,18 @@ struct StF16S : StF16 {
 
 // ------------------------------------------------------------ launch order
 // The hardware hands consecutive workgroups of a grid to the 8 XCDs in turn
-// (workgroup b runs on XCD b mod 8), each XCD with its own L2.  Renumbering so
-// that XCD k takes the k-th contiguous eighth of the blocks keeps every XCD on
-// its own contiguous stretch of each population plane (and of the shifted
-// storage's neighbour records).  A bijection of [0, G) for any G.
+// (workgroup b runs on XCD b mod 8), each XCD with its own L2.  The grouped
+// order renumbers blocks so that each XCD takes groups of G consecutive blocks
+// (group j of the grid goes to XCD j mod 8): neighbouring rows then share an
+// L2 (the shifted storage re-reads each record from up to 12 neighbours),
+// while the 8 XCDs still sweep nearby addresses.  A bijection of [0, nb); the
+// tail that does not fill a round of 8 groups keeps its numbering.
 constexpr uint32_t kXCDs = 8;
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
-    const uint32_t q = G / kXCDs, r = G % kXCDs, k = b % kXCDs;
-    return k * q + (k < r ? k : r) + b / kXCDs;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t G) {
+    const uint32_t full = nb / (kXCDs * G) * (kXCDs * G);
+    if (b >= full) return b;
+    const uint32_t x = b % kXCDs, i = b / kXCDs;  // XCD, and the block's index on it
+    return ((i / G) * kXCDs + x) * G + i % G;
 }
 
 // ------------------------------------------------------------ population layout

@@ -99,8 +99,9 @@ struct StepArgs {
     float *E_out;
     // shifted storage: the two record planes (uint4 [N] each), else null
     void *rec[2];
-    // 1: blocks take rows in XCD-contiguous order (see xcd_block)
-    uint32_t xcd_order;
+    // > 0: blocks in the grouped XCD order with groups of this many blocks
+    // (see xcd_block); 0: hardware order
+    uint32_t xcd_group;
 };
 
 

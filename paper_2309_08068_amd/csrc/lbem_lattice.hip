@@ -33,7 +33,7 @@ template <class M, int ODD, class ST>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     constexpr int NW = kBlock / 64;
     __shared__ double sm_en[NW], sm_det[NW];
-    const uint32_t blk = a.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t blk = a.xcd_group ? xcd_block(blockIdx.x, gridDim.x, a.xcd_group) : blockIdx.x;
     const uint32_t c = blk * kBlock + threadIdx.x;
     const bool live = c < a.N;
     const uint32_t cc = live ? c : a.N - 1;
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
     using T = typename ST::T;
     __shared__ T sh[(ODD && !DIRECT) ? n_xshift<M>() : 1][RB];
     __shared__ double sm_en[NW], sm_det[NW];
-    const uint32_t blk = a.xcd_order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t blk = a.xcd_group ? xcd_block(blockIdx.x, gridDim.x, a.xcd_group) : blockIdx.x;
     const uint32_t row = blk / SEG, seg = blk % SEG;  // row = y + ny z
     const uint32_t x = seg * TB + threadIdx.x;
     const uint32_t z = row / a.ny;
@@ -426,10 +426,10 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     lat->plane_z = -1;
     lat->det_z = -1;
     lat->t = 0;
-    // default launch tuning (measured on MI355X at 256^3): late store addresses
-    // on the odd parity except for MM with FP32 storage, no occupancy cap
-    lat->tune_form[0] = 0;
-    lat->tune_form[1] = (desc->model == LBEM_MM && desc->storage == LBEM_F32) ? 0 : 1;
+    // default launch tuning (measured on MI355X at 256^3): early store
+    // addresses for FP32 storage, late ones for the 16-bit formats, hardware
+    // block order, no occupancy cap
+    lat->tune_form[0] = lat->tune_form[1] = desc->storage == LBEM_F32 ? 0 : 1;
     lat->tune_cap[0] = lat->tune_cap[1] = 0;
     lat->tune_pad[0] = lat->tune_pad[1] = 0;
     hipStream_t s = lat->stream;
@@ -728,7 +728,9 @@ void lbem::dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd) {
     const void *k = step_kernel_of(lat, odd, lat->tune_form[odd] & 3);
     const uint32_t rb = row_block(&lat->d), seg = step_segments(lat, odd);
     StepArgs b = a;
-    b.xcd_order = uint32_t(lat->tune_form[odd] >> 2) & 1u;
+    // grouped order: one layout chunk of rows (at least 16 rows) per group
+    const uint32_t rows_per_group = lat->pl.rshift < 31 ? std::max(16u, 1u << lat->pl.rshift) : 16u;
+    b.xcd_group = (lat->tune_form[odd] >> 2) & 1 ? rows_per_group * seg : 0u;
     void *args[] = {&b};
     (void)hipLaunchKernel(k, dim3(lat->nblocks * seg), dim3(rb ? rb / seg : kBlock), args, lat->tune_pad[odd],
                           lat->stream);
@@ -922,7 +924,7 @@ lbem_status lbem_set_tuning(lbem_lattice *lat, const int32_t *form, const int32_
     if (!lat || !form || !blocks_per_cu) return fail(LBEM_EINVAL, "null argument");
     for (int p = 0; p < 2; ++p) {
         if (form[p] < 0 || form[p] > 7)
-            return fail(LBEM_EINVAL, "form must be 0, 1, 2 or 3, plus 4 for the XCD-contiguous order");
+            return fail(LBEM_EINVAL, "form must be 0, 1, 2 or 3, plus 4 for the grouped XCD order");
         if (blocks_per_cu[p] < 0 || blocks_per_cu[p] > 64) return fail(LBEM_EINVAL, "blocks_per_cu must be in [0, 64]");
     }
     for (int p = 0; p < 2; ++p) {
