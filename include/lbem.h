@@ -132,14 +132,23 @@ lbem_status lbem_set_stream(lbem_lattice *lat, void *stream);
  * for HV.  E, B: dev float [3][N].  Resets the time level to 0. */
 lbem_status lbem_set_fields(lbem_lattice *lat, const float *E, const float *B);
 
-/* Soft current source (Section IV-C, Appendix B note): at time level n the
+/* Soft current sources (Section IV-C, Appendix B note): at time level n the
  * cells get J_src = J0[k] sin(2 pi n / period + phase), which enters the
  * current of eq. (MacorscopicCurrentMiller) for MM and the source term of eq.
- * (SourceTermHV) for HV.  cells: host int64 [n] distinct cell indices; J0:
- * host float [n][3].  n = 0 removes the source.  n <= LBEM_MAX_SOURCES,
- * period > 0.  Synchronises the stream. */
+ * (SourceTermHV) for HV.  Replaces every source set before.  cells: host int64
+ * [n] distinct cell indices; J0: host float [n][3].  n = 0 removes all
+ * sources.  n <= LBEM_MAX_SOURCES, period > 0.  Synchronises the stream.  The
+ * weight sin(...) is evaluated in FP64 with whole periods removed first. */
 lbem_status lbem_set_current_source(lbem_lattice *lat, int32_t n, const int64_t *cells, const float *J0,
                                     double period, double phase);
+
+/* Add one soft point current at cell (x, y, z) with its own period and phase:
+ * J_src(n) = J0 sin(2 pi n / period + phase) (Section IV-C), alongside the
+ * sources already set.  J0: host float [3].  LBEM_EINVAL if the cell is outside
+ * the lattice or already has a source, or the list is full.  Synchronises the
+ * stream. */
+lbem_status lbem_add_point_current(lbem_lattice *lat, int32_t x, int32_t y, int32_t z, const float *J0, double period,
+                                   double phase);
 
 /* Hard plane source (Appendix B "impose fields"): after the collision of step
  * n, every cell of the plane z gets f' = f_eq(E_imp, B_imp, J = 0) with
@@ -256,6 +265,20 @@ lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, i
  * and keeps the fastest for later calls. */
 lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, const float *E0, const float *B0,
                                   double scale, double *grad_eps, double *grad_sigma);
+
+/* Launch tuning of the adjoint kernel per parity of the reverse pass, as
+ * lbem_set_tuning (form 0, 1 or 2; no split rows, no block order).  Setting it
+ * skips the timing that the first lbem_adjoint_backward would do; results are
+ * bit-identical for every choice.  get returns -1 before either happened. */
+lbem_status lbem_set_adjoint_tuning(lbem_lattice *lat, const int32_t *form, const int32_t *blocks_per_cu);
+lbem_status lbem_get_adjoint_tuning(lbem_lattice *lat, int32_t *form, int32_t *blocks_per_cu);
+
+/* Both passes in one call: lbem_adjoint_forward(nsteps, K, keep, det_z, loss)
+ * then lbem_adjoint_backward(E0, B0, scale, grad_eps, grad_sigma), with the
+ * same arguments, workspace and errors. */
+lbem_status lbem_adjoint(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z, const float *E0,
+                         const float *B0, double scale, double *grad_eps, double *grad_sigma, double *loss, void *ws,
+                         size_t ws_bytes);
 
 /* ------------------------------------------------------------------------
  * Batched ragged 1-D lattices (Section IV-D generalised to many stacks).

@@ -545,3 +545,35 @@ lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, 
     if (st) return st;
     return hip_check(hipGetLastError(), "adjoint");
 }
+
+lbem_status lbem_adjoint(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z, const float *E0,
+                         const float *B0, double scale, double *grad_eps, double *grad_sigma, double *loss, void *ws,
+                         size_t ws_bytes) {
+    lbem_status st = lbem_adjoint_forward(lat, nsteps, K, keep, det_z, ws, ws_bytes, loss);
+    if (st) return st;
+    return lbem_adjoint_backward(lat, ws, ws_bytes, E0, B0, scale, grad_eps, grad_sigma);
+}
+
+lbem_status lbem_set_adjoint_tuning(lbem_lattice *lat, const int32_t *form, const int32_t *blocks_per_cu) {
+    if (!lat || !form || !blocks_per_cu) return fail(LBEM_EINVAL, "null argument");
+    for (int p = 0; p < 2; ++p) {
+        if (form[p] < 0 || form[p] > 2) return fail(LBEM_EINVAL, "adjoint form must be 0, 1 or 2");
+        if (blocks_per_cu[p] < 0 || blocks_per_cu[p] > 64) return fail(LBEM_EINVAL, "blocks_per_cu must be in [0, 64]");
+    }
+    for (int p = 0; p < 2; ++p) {
+        lat->adj_form[p] = form[p];
+        lat->adj_cap[p] = blocks_per_cu[p];
+        lat->adj_pad[p] = lds_pad_for(adjoint_ptr(lat, p, form[p]), blocks_per_cu[p]);
+    }
+    lat->adj_tuned = 1;
+    return LBEM_OK;
+}
+
+lbem_status lbem_get_adjoint_tuning(lbem_lattice *lat, int32_t *form, int32_t *blocks_per_cu) {
+    if (!lat || !form || !blocks_per_cu) return fail(LBEM_EINVAL, "null argument");
+    for (int p = 0; p < 2; ++p) {
+        form[p] = lat->adj_tuned ? lat->adj_form[p] : -1;
+        blocks_per_cu[p] = lat->adj_tuned ? lat->adj_cap[p] : -1;
+    }
+    return LBEM_OK;
+}

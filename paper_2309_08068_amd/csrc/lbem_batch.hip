@@ -95,7 +95,7 @@ __global__ __launch_bounds__(T) void batch_persistent(BatchArgs a) {
                 for (uint32_t i = threadIdx.x; i < L; i += T)
                     cell_1d<M, 1, ST>(pop, a.pl, a.eps, a.mu, a.sig, s, L, i, nullptr);
             }
-            __syncthreads();  // the next step reads what neighbouring threads wrote
+            lds_phase_barrier();  // the next step reads what neighbouring threads wrote
         }
     }
 }

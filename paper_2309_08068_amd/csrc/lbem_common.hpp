@@ -235,6 +235,17 @@ constexpr int n_xshift() {
     return n;
 }
 
+// Workgroup barrier around a phase change of a reused LDS array.  The
+// compiler is kept from moving any memory access across it (empty asm with a
+// memory clobber on both sides): the backend has been seen to sink LDS reads
+// below a plain __syncthreads() under register pressure, after which other
+// threads overwrite the array.
+__device__ __forceinline__ void lds_phase_barrier() {
+    asm volatile("" ::: "memory");
+    __syncthreads();
+    asm volatile("" ::: "memory");
+}
+
 // Gather / scatter of the in-place AA streaming for a block that owns one
 // whole x-row of RB cells (y, z uniform).  Every HBM access is the aligned
 // row segment of one population plane, with the non-temporal hint; the +-1 x
@@ -298,12 +309,16 @@ struct RowIO {
                 if (M::vel(q, 0) == 0) f[q] = ST::cvt(v, inv_scale);
                 else sh[k++][x] = v;
             }
-            __syncthreads();
+            lds_phase_barrier();
             k = 0;
 #pragma unroll
             for (int q = 0; q < M::Q; ++q)
                 if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][(x + RB - M::vel(q, 0)) % RB], inv_scale);
-            __syncthreads();
+            // every LDS value in a register before other threads may overwrite sh
+#pragma unroll
+            for (int q = 0; q < M::Q; ++q)
+                if (M::vel(q, 0) != 0) asm volatile("" : "+v"(f[q]));
+            lds_phase_barrier();
         }
     }
 
@@ -320,7 +335,7 @@ struct RowIO {
                 if (M::vel(q, 0) == 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
                 else sh[k++][(x + M::vel(q, 0) + RB) % RB] = ST::pack(f[q], scale);
             }
-            __syncthreads();
+            lds_phase_barrier();
             k = 0;
 #pragma unroll
             for (int q = 0; q < M::Q; ++q)

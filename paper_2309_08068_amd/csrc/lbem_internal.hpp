@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/lbem.h"
 #include "lbem_common.hpp"
 
@@ -12,7 +14,8 @@ namespace lbem {
 
 // Byte offsets of the regions of a lattice workspace.
 struct WsLayout {
-    size_t pop, rec, eps, mu, sig, en_part, det_part, src_blk, src_cell, src_J0, prb_blk, prb_cell, prb_slot, flags;
+    size_t pop, rec, eps, mu, sig, en_part, det_part, src_blk, src_cell, src_J0, src_tp, prb_blk, prb_cell, prb_slot,
+        flags;
     size_t det_cap;  // detector partial slots
     size_t total;
 };
@@ -70,7 +73,6 @@ lbem_status fail(lbem_status st, const char *fmt, ...);
 lbem_status hip_check(hipError_t e, const char *what);
 
 // 2 pi n / period + phase with whole periods removed in double precision.
-double two_pi_frac(double n, double period, double phase);
 
 // Arguments of one launch of the 3-D step kernel.
 struct StepArgs {
@@ -79,10 +81,12 @@ struct StepArgs {
     const float *eps, *mu, *sig;
     uint32_t nx, ny, nz, N;
     float scale, inv_scale;
-    // soft current source: per-block ranges into a cell-sorted list
+    // soft current sources: per-block ranges into a cell-sorted list; source k
+    // carries J0[3k..3k+2] sin(2 pi t / tp[2k] + tp[2k+1]) at time level src_t
     const int32_t *src_blk, *src_cell;
     const float *src_J0;
-    float src_w;
+    const double *src_tp;
+    double src_t;
     // hard plane source
     int32_t plane_z;
     float Eimp[3], Bimp[3];
@@ -121,9 +125,11 @@ struct lbem_lattice {
     size_t ws_bytes;
     lbem::WsLayout L;
     lbem::PopLayout pl;
-    // sources
+    // sources (host copy of the list, in the order given)
     int32_t nsrc;
-    double src_period, src_phase;
+    std::vector<int32_t> src_cells;
+    std::vector<float> src_J0;
+    std::vector<double> src_tp;
     int32_t plane_z;
     float pE0[3], pB0[3];
     double plane_period;
@@ -156,6 +162,12 @@ struct lbem_lattice {
 
 
 namespace lbem {
+// Amplitude weight sin(2 pi t / period + phase) of a soft source, with the
+// whole periods removed from t / period first (same on host and device).
+__host__ __device__ inline double source_weight(double t, double period, double phase) {
+    const double r = t / period;
+    return sin(2.0 * M_PI * (r - floor(r)) + phase);
+}
 // Step-kernel arguments for the lattice's current configuration (no
 // observation or frame output set).
 StepArgs base_step_args(lbem_lattice *lat);

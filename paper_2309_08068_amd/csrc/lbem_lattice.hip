@@ -59,9 +59,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
         const int s0 = a.src_blk[blk], s1 = a.src_blk[blk + 1];
         for (int k = s0; k < s1; ++k)
             if (a.src_cell[k] == int32_t(c)) {
-                Js[0] = a.src_J0[3 * k] * a.src_w;
-                Js[1] = a.src_J0[3 * k + 1] * a.src_w;
-                Js[2] = a.src_J0[3 * k + 2] * a.src_w;
+                const float w = float(source_weight(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]));
+                Js[0] = a.src_J0[3 * k] * w;
+                Js[1] = a.src_J0[3 * k + 1] * w;
+                Js[2] = a.src_J0[3 * k + 2] * w;
             }
     }
     CellFields o;
@@ -144,9 +145,10 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
         const int s0 = a.src_blk[row], s1 = a.src_blk[row + 1];
         for (int k = s0; k < s1; ++k)
             if (a.src_cell[k] == int32_t(c)) {
-                Js[0] = a.src_J0[3 * k] * a.src_w;
-                Js[1] = a.src_J0[3 * k + 1] * a.src_w;
-                Js[2] = a.src_J0[3 * k + 2] * a.src_w;
+                const float w = float(source_weight(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]));
+                Js[0] = a.src_J0[3 * k] * w;
+                Js[1] = a.src_J0[3 * k + 1] * w;
+                Js[2] = a.src_J0[3 * k + 2] * w;
             }
     }
     CellFields o;
@@ -200,7 +202,8 @@ struct ObsArgs {
     float inv_scale;
     const int32_t *src_blk, *src_cell;
     const float *src_J0;
-    float src_w;
+    const double *src_tp;
+    double src_t;
     float *E, *B, *D, *H;
     double *en_part;
     const void *rec;  // shifted storage: the record plane this state's reader uses
@@ -229,9 +232,10 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
         const int s0 = a.src_blk[u], s1 = a.src_blk[u + 1];
         for (int k = s0; k < s1; ++k)
             if (a.src_cell[k] == int32_t(c)) {
-                Js[0] = a.src_J0[3 * k] * a.src_w;
-                Js[1] = a.src_J0[3 * k + 1] * a.src_w;
-                Js[2] = a.src_J0[3 * k + 2] * a.src_w;
+                const float w = float(source_weight(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]));
+                Js[0] = a.src_J0[3 * k] * w;
+                Js[1] = a.src_J0[3 * k + 1] * w;
+                Js[2] = a.src_J0[3 * k + 2] * w;
             }
     }
     CellFields o;
@@ -364,6 +368,7 @@ WsLayout layout(const lbem_desc *d) {
     L.src_blk = take((nblocks + 1) * 4);
     L.src_cell = take(size_t(LBEM_MAX_SOURCES) * 4);
     L.src_J0 = take(size_t(LBEM_MAX_SOURCES) * 12);
+    L.src_tp = take(size_t(LBEM_MAX_SOURCES) * 16);
     L.prb_blk = take((nblocks + 1) * 4);
     L.prb_cell = take(size_t(LBEM_MAX_PROBES) * 4);
     L.prb_slot = take(size_t(LBEM_MAX_PROBES) * 4);
@@ -527,43 +532,93 @@ static std::vector<int32_t> block_ranges(const std::vector<int32_t> &sorted_cell
     return r;
 }
 
-lbem_status lbem_set_current_source(lbem_lattice *lat, int32_t n, const int64_t *cells, const float *J0,
-                                    double period, double phase) {
-    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
-    if (n < 0 || n > LBEM_MAX_SOURCES) return fail(LBEM_EINVAL, "source count %d outside [0, %d]", n, LBEM_MAX_SOURCES);
+// Upload the lattice's source list (sorted by cell, per-block ranges).
+static lbem_status upload_sources(lbem_lattice *lat) {
+    const int32_t n = int32_t(lat->src_cells.size());
     if (n == 0) {
         lat->nsrc = 0;
         return LBEM_OK;
     }
-    if (!cells || !J0) return fail(LBEM_EINVAL, "null source arrays");
-    if (!(period > 0.0) || !std::isfinite(period) || !std::isfinite(phase))
-        return fail(LBEM_EINVAL, "period must be finite and > 0");
     std::vector<int32_t> order(n);
-    for (int32_t k = 0; k < n; ++k) {
-        if (cells[k] < 0 || cells[k] >= int64_t(lat->N)) return fail(LBEM_EINVAL, "source cell %lld out of range", (long long)cells[k]);
-        if (!std::isfinite(J0[3 * k]) || !std::isfinite(J0[3 * k + 1]) || !std::isfinite(J0[3 * k + 2]))
-            return fail(LBEM_ENOTFINITE, "source amplitude %d is not finite", k);
-        order[k] = k;
-    }
-    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cells[a] < cells[b]; });
+    for (int32_t k = 0; k < n; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return lat->src_cells[a] < lat->src_cells[b]; });
     std::vector<int32_t> sc(n);
     std::vector<float> sj(3 * size_t(n));
+    std::vector<double> tp(2 * size_t(n));
     for (int32_t k = 0; k < n; ++k) {
-        sc[k] = int32_t(cells[order[k]]);
-        if (k && sc[k] == sc[k - 1]) return fail(LBEM_EINVAL, "source cell %d repeated", sc[k]);
-        for (int a = 0; a < 3; ++a) sj[3 * k + a] = J0[3 * order[k] + a];
+        const int32_t o = order[k];
+        sc[k] = lat->src_cells[o];
+        for (int a = 0; a < 3; ++a) sj[3 * k + a] = lat->src_J0[3 * size_t(o) + a];
+        tp[2 * k] = lat->src_tp[2 * size_t(o)];
+        tp[2 * k + 1] = lat->src_tp[2 * size_t(o) + 1];
     }
     std::vector<int32_t> br = block_ranges(sc, lat->nblocks, lat->bu);
     hipStream_t s = lat->stream;
     lbem_status st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_blk, br.data(), br.size() * 4, hipMemcpyHostToDevice, s), "copy");
     if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_cell, sc.data(), sc.size() * 4, hipMemcpyHostToDevice, s), "copy");
     if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_J0, sj.data(), sj.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipMemcpyAsync(lat->ws + lat->L.src_tp, tp.data(), tp.size() * 8, hipMemcpyHostToDevice, s), "copy");
     if (!st) st = hip_check(hipStreamSynchronize(s), "synchronise");
-    if (st) return st;
-    lat->nsrc = n;
-    lat->src_period = period;
-    lat->src_phase = phase;
+    if (!st) lat->nsrc = n;
+    return st;
+}
+
+static lbem_status check_source(const lbem_lattice *lat, int64_t cell, const float *J0, double period, double phase) {
+    if (cell < 0 || cell >= int64_t(lat->N)) return fail(LBEM_EINVAL, "source cell %lld out of range", (long long)cell);
+    if (!std::isfinite(J0[0]) || !std::isfinite(J0[1]) || !std::isfinite(J0[2]))
+        return fail(LBEM_ENOTFINITE, "source amplitude is not finite");
+    if (!(period > 0.0) || !std::isfinite(period) || !std::isfinite(phase))
+        return fail(LBEM_EINVAL, "period must be finite and > 0, phase finite");
     return LBEM_OK;
+}
+
+lbem_status lbem_set_current_source(lbem_lattice *lat, int32_t n, const int64_t *cells, const float *J0,
+                                    double period, double phase) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (n < 0 || n > LBEM_MAX_SOURCES) return fail(LBEM_EINVAL, "source count %d outside [0, %d]", n, LBEM_MAX_SOURCES);
+    if (n > 0 && (!cells || !J0)) return fail(LBEM_EINVAL, "null source arrays");
+    std::vector<int32_t> sc(n);
+    for (int32_t k = 0; k < n; ++k) {
+        lbem_status st = check_source(lat, cells[k], J0 + 3 * size_t(k), period, phase);
+        if (st) return st;
+        sc[k] = int32_t(cells[k]);
+    }
+    std::vector<int32_t> sorted = sc;
+    std::sort(sorted.begin(), sorted.end());
+    for (int32_t k = 1; k < n; ++k)
+        if (sorted[k] == sorted[k - 1]) return fail(LBEM_EINVAL, "source cell %d repeated", sorted[k]);
+    lat->src_cells = sc;
+    lat->src_J0.assign(J0, J0 + 3 * size_t(n));
+    lat->src_tp.resize(2 * size_t(n));
+    for (int32_t k = 0; k < n; ++k) {
+        lat->src_tp[2 * size_t(k)] = period;
+        lat->src_tp[2 * size_t(k) + 1] = phase;
+    }
+    return upload_sources(lat);
+}
+
+lbem_status lbem_add_point_current(lbem_lattice *lat, int32_t x, int32_t y, int32_t z, const float *J0, double period,
+                                   double phase) {
+    if (!lat || !J0) return fail(LBEM_EINVAL, "null argument");
+    if (x < 0 || y < 0 || z < 0 || x >= lat->d.nx || y >= lat->d.ny || z >= lat->d.nz)
+        return fail(LBEM_EINVAL, "cell (%d, %d, %d) outside the lattice", x, y, z);
+    if (lat->src_cells.size() >= size_t(LBEM_MAX_SOURCES)) return fail(LBEM_EINVAL, "too many sources");
+    const int64_t cell = int64_t(x) + int64_t(lat->d.nx) * (int64_t(y) + int64_t(lat->d.ny) * z);
+    lbem_status st = check_source(lat, cell, J0, period, phase);
+    if (st) return st;
+    for (int32_t c : lat->src_cells)
+        if (c == int32_t(cell)) return fail(LBEM_EINVAL, "cell (%d, %d, %d) already has a source", x, y, z);
+    lat->src_cells.push_back(int32_t(cell));
+    for (int a = 0; a < 3; ++a) lat->src_J0.push_back(J0[a]);
+    lat->src_tp.push_back(period);
+    lat->src_tp.push_back(phase);
+    st = upload_sources(lat);
+    if (st) {  // keep the host list equal to what the device holds
+        lat->src_cells.pop_back();
+        lat->src_J0.resize(lat->src_J0.size() - 3);
+        lat->src_tp.resize(lat->src_tp.size() - 2);
+    }
+    return st;
 }
 
 lbem_status lbem_set_plane_source(lbem_lattice *lat, int32_t z, const float *E0, const float *B0, double period) {
@@ -736,13 +791,6 @@ void lbem::dispatch_step(const lbem_lattice *lat, const StepArgs &a, int odd) {
                           lat->stream);
 }
 
-namespace lbem {
-double two_pi_frac(double n, double period, double phase) {
-    // 2 pi n / period + phase, with the integer number of periods removed first
-    const double r = n / period;
-    return 2.0 * M_PI * (r - std::floor(r)) + phase;
-}
-}  // namespace lbem
 
 StepArgs lbem::base_step_args(lbem_lattice *lat) {
     const WsLayout &L = lat->L;
@@ -762,6 +810,7 @@ StepArgs lbem::base_step_args(lbem_lattice *lat) {
         a.src_blk = reinterpret_cast<const int32_t *>(lat->ws + L.src_blk);
         a.src_cell = reinterpret_cast<const int32_t *>(lat->ws + L.src_cell);
         a.src_J0 = reinterpret_cast<const float *>(lat->ws + L.src_J0);
+        a.src_tp = reinterpret_cast<const double *>(lat->ws + L.src_tp);
     }
     a.plane_z = lat->plane_z;
     a.det_z = -1;
@@ -795,9 +844,9 @@ lbem_status lbem::step_impl(lbem_lattice *lat, int64_t nsteps, float *frames) {
     double *en_part = reinterpret_cast<double *>(lat->ws + L.en_part);
     for (int64_t s = 0; s < nsteps; ++s) {
         const int64_t t = lat->t;
-        if (lat->nsrc > 0) a.src_w = float(std::sin(two_pi_frac(double(t), lat->src_period, lat->src_phase)));
+        a.src_t = double(t);
         if (lat->plane_z >= 0) {
-            const double w = std::sin(two_pi_frac(double(t), lat->plane_period, 0.0));
+            const double w = source_weight(double(t), lat->plane_period, 0.0);
             for (int k = 0; k < 3; ++k) {
                 a.Eimp[k] = float(lat->pE0[k] * w);
                 a.Bimp[k] = float(lat->pB0[k] * w);
@@ -859,7 +908,8 @@ static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, floa
         a.src_blk = reinterpret_cast<const int32_t *>(lat->ws + L.src_blk);
         a.src_cell = reinterpret_cast<const int32_t *>(lat->ws + L.src_cell);
         a.src_J0 = reinterpret_cast<const float *>(lat->ws + L.src_J0);
-        a.src_w = float(std::sin(two_pi_frac(double(lat->t), lat->src_period, lat->src_phase)));
+        a.src_tp = reinterpret_cast<const double *>(lat->ws + L.src_tp);
+        a.src_t = double(lat->t);
     }
     a.E = E;
     a.B = B;

@@ -35,6 +35,7 @@ SIGNATURES = {
     "lbem_set_fields": (_I32, [_P, _P, _P]),
     "lbem_set_current_source": (_I32, [_P, _I32, _P, _P, _D, _D]),
     "lbem_set_plane_source": (_I32, [_P, _I32, _P, _P, _D]),
+    "lbem_add_point_current": (_I32, [_P, _I32, _I32, _I32, _P, _D, _D]),
     "lbem_set_probes": (_I32, [_P, _I32, _P, _I64, _P]),
     "lbem_set_detector": (_I32, [_P, _I32]),
     "lbem_detector_read": (_I32, [_P, _P]),
@@ -51,6 +52,9 @@ SIGNATURES = {
     "lbem_adjoint_workspace_size": (_I32, [_P, _I64, _I32, _I32, C.POINTER(_SZ)]),
     "lbem_adjoint_forward": (_I32, [_P, _I64, _I32, _I32, _I32, _P, _SZ, _P]),
     "lbem_adjoint_backward": (_I32, [_P, _P, _SZ, _P, _P, _D, _P, _P]),
+    "lbem_adjoint": (_I32, [_P, _I64, _I32, _I32, _I32, _P, _P, _D, _P, _P, _P, _P, _SZ]),
+    "lbem_set_adjoint_tuning": (_I32, [_P, _P, _P]),
+    "lbem_get_adjoint_tuning": (_I32, [_P, _P, _P]),
     "lbem_batch_workspace_size": (_I32, [_I32, _I32, _I32, _P, C.POINTER(_SZ)]),
     "lbem_batch_create": (_I32, [_I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P, C.POINTER(_P)]),
     "lbem_batch_destroy": (_I32, [_P]),
@@ -182,15 +186,27 @@ class Lattice:
                                                J0.ctypes.data_as(C.c_void_p), float(period), float(phase)))
 
     def set_currents(self, currents):
-        """Point currents as (cell, J0[3], period, phase) sharing one period and phase."""
+        """Point currents as (cell, J0[3], period, phase); replaces all sources."""
         if not currents:
             check(self.lib.lbem_set_current_source(self.h, 0, None, None, 1.0, 0.0))
             return
         periods = {c[2] for c in currents}
         phases = {c[3] for c in currents}
-        if len(periods) != 1 or len(phases) != 1:
-            raise ValueError("all currents of a lattice share one period and phase")
-        self.set_current_source([c[0] for c in currents], [c[1] for c in currents], periods.pop(), phases.pop())
+        if len(periods) == 1 and len(phases) == 1:
+            self.set_current_source([c[0] for c in currents], [c[1] for c in currents], periods.pop(), phases.pop())
+            return
+        check(self.lib.lbem_set_current_source(self.h, 0, None, None, 1.0, 0.0))
+        nx, ny, _ = self.shape
+        for cell, J0, period, phase in currents:
+            cell = int(cell)
+            self.add_point_current((cell % nx, (cell // nx) % ny, cell // (nx * ny)), J0, period, phase)
+
+    def add_point_current(self, xyz, J0, period: float, phase: float = 0.0):
+        """One more soft point current at cell (x, y, z) with its own period and phase."""
+        J0 = np.ascontiguousarray(np.asarray(J0, dtype=np.float32).reshape(3))
+        x, y, z = (int(v) for v in xyz)
+        check(self.lib.lbem_add_point_current(self.h, x, y, z, J0.ctypes.data_as(C.c_void_p), float(period),
+                                              float(phase)))
 
     def set_plane_source(self, z: int, E0, B0, period: float):
         E0 = np.ascontiguousarray(np.asarray(E0, dtype=np.float32))
@@ -280,6 +296,17 @@ class Lattice:
         return self.tuning()
 
     # ------------------------------------------------------------ adjoint
+    def set_adjoint_tuning(self, form, blocks_per_cu):
+        f = (C.c_int32 * 2)(*form)
+        c = (C.c_int32 * 2)(*blocks_per_cu)
+        check(self.lib.lbem_set_adjoint_tuning(self.h, f, c))
+
+    def adjoint_tuning(self):
+        f = (C.c_int32 * 2)()
+        c = (C.c_int32 * 2)()
+        check(self.lib.lbem_get_adjoint_tuning(self.h, f, c))
+        return list(f), list(c)
+
     def adjoint_workspace(self, nsteps: int, K: int, keep: int = 1) -> torch.Tensor:
         size = C.c_size_t()
         check(self.lib.lbem_adjoint_workspace_size(C.byref(self._desc), int(nsteps), int(K), int(keep),
@@ -308,6 +335,19 @@ class Lattice:
                                              _ptr(ge), _ptr(gs)))
         self._keep["adjoint_fields0"] = (E0, B0)
         return ge, gs
+
+    def adjoint(self, nsteps: int, K: int, det_z: int, ws: torch.Tensor, keep: int = 1, E0=None, B0=None,
+                scale: float = 1.0):
+        """Both passes in one library call: (loss, dL/deps_r, dL/dsigma)."""
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        ge = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        gs = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        E0 = _dev_f32(E0, 3 * self.n, self.device)
+        B0 = _dev_f32(B0, 3 * self.n, self.device)
+        check(self.lib.lbem_adjoint(self.h, int(nsteps), int(K), int(keep), int(det_z), _ptr(E0), _ptr(B0),
+                                    float(scale), _ptr(ge), _ptr(gs), _ptr(loss), _ptr(ws), ws.numel()))
+        self._keep["adjoint_fields0"] = (E0, B0)
+        return loss, ge, gs
 
 
 class Batch:

@@ -89,6 +89,48 @@ def test_adjoint_leaves_forward_state():
     assert torch.equal(lat.fields()[0], E1)
 
 
+@pytest.mark.parametrize("model", ["mm", "hv"])
+def test_one_call_adjoint_equals_two_passes(model):
+    """lbem_adjoint gives the bits of lbem_adjoint_forward + lbem_adjoint_backward."""
+    shape = (128, 3, 12)
+    d = smooth_case(shape, 4)
+    out = []
+    for one_call in (False, True):
+        lat = lbem.Lattice(model, shape, d["eps"], d["mu"], d["sig"])
+        lat.set_fields(d["E0"], d["B0"])
+        ws = lat.adjoint_workspace(30, 7, 2)
+        if one_call:
+            loss, ge, gs = lat.adjoint(30, 7, 8, ws, 2, d["E0"], d["B0"])
+        else:
+            loss = lat.adjoint_forward(30, 7, 8, ws, 2)
+            ge, gs = lat.adjoint_backward(ws, d["E0"], d["B0"])
+        out.append((loss.clone(), ge.clone(), gs.clone()))
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("model", ["hv", "mm"])
+def test_adjoint_launch_forms_are_bit_identical(model):
+    """Every launch form of the adjoint kernel (LDS x-shifts with early or late
+    store addresses, direct addressing), per parity, gives the same bits, twice
+    in a row, on a lattice of two layout chunks; the automatic choice too."""
+    shape, nsteps, K = (128, 1, 520), 12, 5
+    d = smooth_case(shape, 5)
+    ref = None
+    for form in ((0, 0), (1, 1), (2, 2), (0, 2), (2, 0), (1, 0), None, (0, 0)):
+        lat = lbem.Lattice(model, shape, d["eps"], d["mu"], d["sig"])
+        if form is not None:
+            lat.set_adjoint_tuning(form, (0, 0))
+        lat.set_fields(d["E0"], d["B0"])
+        ws = lat.adjoint_workspace(nsteps, K, 1)
+        _, ge, gs = lat.adjoint(nsteps, K, shape[2] - 4, ws, 1, d["E0"], d["B0"])
+        if form is None:
+            assert all(f in (0, 1, 2) for f in lat.adjoint_tuning()[0])
+        if ref is None:
+            ref = (ge.clone(), gs.clone())
+        assert torch.equal(ge, ref[0]) and torch.equal(gs, ref[1]), form
+
+
 def test_adjoint_rejects_sources_and_bad_arguments():
     lat = lbem.Lattice("hv", (4, 4, 4))
     ws = torch.empty(256, dtype=torch.uint8, device="cuda")

@@ -100,6 +100,30 @@ def test_random_state_parity(model, shape, steps):
         assert rel(g[k], o[k]) < TOL, (k, rel(g[k], o[k]))
 
 
+@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("shape", [(9, 7, 11), (128, 5, 40)])
+def test_point_currents_with_own_period_and_phase(model, shape):
+    """Soft point currents added one by one (lbem_add_point_current), each with
+    its own amplitude, period and phase, against the oracle."""
+    p = random_problem(model, shape, seed=31, n_src=0)
+    rng = np.random.default_rng(32)
+    n = int(np.prod(shape))
+    cells = rng.choice(n, 4, replace=False)
+    p["currents"] = [(int(c), tuple(rng.normal(size=3)), float(T), float(ph))
+                     for c, T, ph in zip(cells, (11.0, 17.5, 40.0, 7.25), (0.0, 0.7, -1.3, 2.9))]
+    g, lat = run_gpu(model, shape, p, 23)
+    o = run_oracle(model, shape, p, 23)
+    for k in "EBDH":
+        assert rel(g[k], o[k]) < TOL, (k, rel(g[k], o[k]))
+    # the same cell twice, a cell outside the lattice and a bad period are rejected
+    nx, ny, _ = shape
+    c0 = int(cells[0])
+    xyz = (c0 % nx, (c0 // nx) % ny, c0 // (nx * ny))
+    for args in ((xyz, (0, 0, 1), 10.0), ((nx, 0, 0), (0, 0, 1), 10.0), ((0, 0, 0), (0, 0, 1), 0.0)):
+        with pytest.raises(lbem.LbemError):
+            lat.add_point_current(*args)
+
+
 # equilibrium-shifted 16-bit storage on random (non-smooth) states: the
 # non-equilibrium remainder is then as large as the population itself, so the
 # error is that of plain 16-bit storage; a wrong neighbour record in the
