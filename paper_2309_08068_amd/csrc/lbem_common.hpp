@@ -314,10 +314,6 @@ struct RowIO {
 #pragma unroll
             for (int q = 0; q < M::Q; ++q)
                 if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][(x + RB - M::vel(q, 0)) % RB], inv_scale);
-            // every LDS value in a register before other threads may overwrite sh
-#pragma unroll
-            for (int q = 0; q < M::Q; ++q)
-                if (M::vel(q, 0) != 0) asm volatile("" : "+v"(f[q]));
             lds_phase_barrier();
         }
     }

@@ -162,11 +162,37 @@ struct lbem_lattice {
 
 
 namespace lbem {
-// Amplitude weight sin(2 pi t / period + phase) of a soft source, with the
-// whole periods removed from t / period first (same on host and device).
-__host__ __device__ inline double source_weight(double t, double period, double phase) {
+// Amplitude weight sin(2 pi t / period + phase) of a soft source (host side:
+// the hard plane source), with the whole periods removed from t / period first.
+inline double source_weight(double t, double period, double phase) {
     const double r = t / period;
     return sin(2.0 * M_PI * (r - floor(r)) + phase);
+}
+
+// The same weight in the step kernels, without a library sine (whose inlined
+// code would raise every kernel's register allocation): the argument is
+// reduced in FP64 to u = (t / period + phase / 2 pi) mod 1 in [-1/2, 1/2],
+// then x = 2 pi u is folded into [-pi/2, pi/2] with sin(x) = sin(+-pi - x), and
+// sin x is the odd Taylor series to x^15 in FP32 (truncation below 1e-9 there;
+// the result is accurate to FP32 rounding, far inside the 1e-5 parity bar).
+__device__ inline float source_weight_dev(double t, double period, double phase) {
+    double u = t / period + phase * (0.5 / M_PI);
+    u -= rint(u);
+    float x = float(u) * 6.28318530717958647692f;
+    const float hp = 1.57079632679489661923f, pi = 3.14159265358979323846f;
+    if (x > hp) x = pi - x;
+    else if (x < -hp) x = -pi - x;
+    const float x2 = x * x;
+    // x (1 - x^2/3! (1 - x^2/(4.5) (1 - ... ))) written as Horner in x^2
+    float p = 1.0f / 1307674368000.0f;            // 1/15!
+    p = p * -x2 + 1.0f / 6227020800.0f;           // 1/13!
+    p = p * -x2 + 1.0f / 39916800.0f;             // 1/11!
+    p = p * -x2 + 1.0f / 362880.0f;               // 1/9!
+    p = p * -x2 + 1.0f / 5040.0f;                 // 1/7!
+    p = p * -x2 + 1.0f / 120.0f;                  // 1/5!
+    p = p * -x2 + 1.0f / 6.0f;                    // 1/3!
+    p = p * -x2 + 1.0f;
+    return x * p;
 }
 // Step-kernel arguments for the lattice's current configuration (no
 // observation or frame output set).

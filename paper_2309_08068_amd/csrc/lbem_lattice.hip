@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
         const int s0 = a.src_blk[blk], s1 = a.src_blk[blk + 1];
         for (int k = s0; k < s1; ++k)
             if (a.src_cell[k] == int32_t(c)) {
-                const float w = float(source_weight(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]));
+                const float w = source_weight_dev(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]);
                 Js[0] = a.src_J0[3 * k] * w;
                 Js[1] = a.src_J0[3 * k + 1] * w;
                 Js[2] = a.src_J0[3 * k + 2] * w;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
         const int s0 = a.src_blk[row], s1 = a.src_blk[row + 1];
         for (int k = s0; k < s1; ++k)
             if (a.src_cell[k] == int32_t(c)) {
-                const float w = float(source_weight(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]));
+                const float w = source_weight_dev(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]);
                 Js[0] = a.src_J0[3 * k] * w;
                 Js[1] = a.src_J0[3 * k + 1] * w;
                 Js[2] = a.src_J0[3 * k + 2] * w;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
         const int s0 = a.src_blk[u], s1 = a.src_blk[u + 1];
         for (int k = s0; k < s1; ++k)
             if (a.src_cell[k] == int32_t(c)) {
-                const float w = float(source_weight(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]));
+                const float w = source_weight_dev(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]);
                 Js[0] = a.src_J0[3 * k] * w;
                 Js[1] = a.src_J0[3 * k + 1] * w;
                 Js[2] = a.src_J0[3 * k + 2] * w;

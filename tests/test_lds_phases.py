@@ -5,7 +5,7 @@ between the gather's first and second workgroup barrier there may only be LDS
 reads and between the second and third only LDS writes.  An LDS read moved
 below the second barrier reads what other threads' scatter already wrote; the
 compiler has produced exactly that under register pressure, which is why the
-kernels pin those values before the barrier."""
+kernels bracket those barriers with compiler memory clobbers."""
 import os
 import re
 import shutil
