@@ -6,8 +6,9 @@ sponge on every face, soft point current J_z = sin(2 pi n / 40) at the centre,
 three field probes recorded every step).  One benchmark step is one time step
 of the whole lattice: gather with in-place streaming, collision, sources,
 scatter and the fused FP64 probe recording.  The headline value is the MM
-model with FP32 population storage; the HV model, BF16 storage and the
-equilibrium-shifted BF16 storage are timed the same way and reported under
+model with FP32 population storage; the HV model, BF16 storage, the
+equilibrium-shifted BF16 storage and the MM scheme in difference form (24
+populations per cell, same E and B) are timed the same way and reported under
 "variants".  Further sections: the batched ragged 1-D multilayer workload, the
 adjoint on the 128 x 128 x 256 inverse-design lattice, the 384^3 precision
 sweep, and the FP64 oracle on the host cores.
@@ -36,7 +37,15 @@ BYTES_PER_LU = {("mm", "f32"): 2 * 50 * 4 + 12, ("mm", "bf16"): 2 * 50 * 2 + 12,
                 ("hv", "f32"): 2 * 36 * 4 + 12, ("hv", "bf16"): 2 * 36 * 2 + 12,
                 ("mm", "f16"): 2 * 50 * 2 + 12, ("hv", "f16"): 2 * 36 * 2 + 12,
                 ("mm", "bf16_shifted"): 2 * 50 * 2 + 12 + 32, ("hv", "bf16_shifted"): 2 * 36 * 2 + 12 + 32,
-                ("mm", "f16_shifted"): 2 * 50 * 2 + 12 + 32, ("hv", "f16_shifted"): 2 * 36 * 2 + 12 + 32}
+                ("mm", "f16_shifted"): 2 * 50 * 2 + 12 + 32, ("hv", "f16_shifted"): 2 * 36 * 2 + 12 + 32,
+                # MM in difference form: 24 populations per cell
+                ("mmd", "f32"): 2 * 24 * 4 + 12, ("mmd", "bf16"): 2 * 24 * 2 + 12,
+                ("mmd", "bf16_shifted"): 2 * 24 * 2 + 12 + 32}
+
+
+def workload_model(model: str) -> str:
+    """The scheme whose workload (media units, sponge, source) a model runs."""
+    return "mm" if model == "mmd" else model
 
 
 # sources the single-lattice step kernels are compiled from
@@ -74,8 +83,8 @@ def time_variant(model: str, storage: str, n: int, steps: int, warmup: int):
     import torch
     from paper_2309_08068_amd import inputs, lbem
 
-    w = inputs.dipole(model, n=n, steps=steps)
-    lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=0.0)
+    w = inputs.dipole(workload_model(model), n=n, steps=steps)
+    lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=0.0, model=model)
     lat.set_probes(w.probes, warmup + 2 * steps + 1)
     tuning = lat.autotune(10)
     stream = torch.cuda.current_stream()
@@ -260,15 +269,15 @@ def main():
     torch.cuda.set_device(0)
 
     variants = [("mm", "f32"), ("mm", "bf16"), ("hv", "f32"), ("hv", "bf16"), ("mm", "bf16_shifted"),
-                ("hv", "bf16_shifted")]
+                ("hv", "bf16_shifted"), ("mmd", "f32"), ("mmd", "bf16"), ("mmd", "bf16_shifted")]
     if args.only:
         keep = set(args.only.split(","))
         variants = [v for v in variants if f"{v[0]}_{v[1]}" in keep]
     if args.profile:
         from paper_2309_08068_amd import inputs, lbem
         for model, storage in variants:
-            w = inputs.dipole(model, n=args.n, steps=args.steps)
-            lat = lbem.lattice_from_workload(w, storage=storage)
+            w = inputs.dipole(workload_model(model), n=args.n, steps=args.steps)
+            lat = lbem.lattice_from_workload(w, storage=storage, model=model)
             lat.set_probes(w.probes, args.steps + 1)
             tuning = lat.autotune(10)
             torch.cuda.synchronize()

@@ -9,6 +9,15 @@
  *            electric and one magnetic 3-vector population each (36 scalars),
  *            with the current source term T_i = -(J.v_i) v_i / 2 of eq.
  *            (SourceTermHV); lattice constants eps0 = mu0 = 3 (speed 1/3).
+ *   LBEM_MM_DIFF  the MM scheme in difference form: 24 populations per cell,
+ *            d_i^{p(r)} = f_{i0}^{p(r)} - f_{i1}^{p(r)}.  D', B (eq.
+ *            MacroscopicFieldsMiller) depend on the populations only through
+ *            these differences, both populations of a pair move along the same
+ *            v_i, and their equilibria (eq. equilibriumsMiller) differ by a
+ *            term free of J, so d' = 2 d_eq - d evolves on its own and gives
+ *            the E, B, D, H of LBEM_MM (equal up to FP32 rounding) at 24 / 50
+ *            of its traffic.  The charge density of the sums and rest
+ *            populations is not represented.  No adjoint (use LBEM_MM).
  * One time step (Appendix B) = collision with tau = 1/2 (moments, constitutive
  * relations and current, equilibria, f' = 2 f_eq - f [+ T]), imposition of hard
  * sources, advection f(x + v_q) <- f'(x).  All boundaries are periodic.
@@ -47,7 +56,7 @@ typedef enum {
     LBEM_ENOTFINITE = -6   /* non-finite media */
 } lbem_status;
 
-typedef enum { LBEM_MM = 0, LBEM_HV = 1 } lbem_model;
+typedef enum { LBEM_MM = 0, LBEM_HV = 1, LBEM_MM_DIFF = 2 } lbem_model;
 
 /* Storage format of the populations.  Collision arithmetic is always FP32;
  * BF16/FP16 only change how populations are held in HBM (round to nearest
@@ -236,7 +245,8 @@ lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t);
  * recomputes each segment storing E(f_n) per step (FP32 frames), then runs
  * the segment's adjoint steps in reverse (in-place AA streaming with reversed
  * velocities).  Gradients accumulate in FP32 over a segment and in FP64
- * across segments.  Both models; no soft or hard sources may be set.
+ * across segments.  LBEM_MM and LBEM_HV (LBEM_MM_DIFF: LBEM_EINVAL); no soft
+ * or hard sources may be set.
  * ------------------------------------------------------------------------ */
 
 /* Bytes of adjoint workspace for nsteps steps with a checkpoint every K steps,

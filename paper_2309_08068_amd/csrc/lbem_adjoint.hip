@@ -422,6 +422,7 @@ lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, i
     lbem_status st = lbem_workspace_size(desc, &dummy);
     if (st) return st;
     if (!bytes) return fail(LBEM_EINVAL, "bytes is NULL");
+    if (desc->model == LBEM_MM_DIFF) return fail(LBEM_EINVAL, "the adjoint is provided for LBEM_MM and LBEM_HV");
     if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
     *bytes = adj_layout(desc, nsteps, K, keep).total;
     return LBEM_OK;
@@ -430,6 +431,7 @@ lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, i
 lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z, void *ws,
                                  size_t ws_bytes, double *loss) {
     if (!lat || !ws || !loss) return fail(LBEM_EINVAL, "null argument");
+    if (lat->d.model == LBEM_MM_DIFF) return fail(LBEM_EINVAL, "the adjoint is provided for LBEM_MM and LBEM_HV");
     if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
     if (lat->nsrc > 0 || lat->plane_z >= 0) return fail(LBEM_ESTATE, "the adjoint needs a lattice without sources");
     if (det_z < 0 || det_z >= lat->d.nz) return fail(LBEM_EINVAL, "detector plane z = %d outside the lattice", det_z);

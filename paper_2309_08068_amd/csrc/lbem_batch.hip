@@ -146,7 +146,7 @@ struct BatchLayout {
 // Chunks of cells with at most kChunkBytes per population plane (as for the
 // 3-D lattice; a row of the layout is one cell); one chunk if all cells fit.
 PopLayout batch_pop_layout(int model, int storage, size_t total) {
-    const uint32_t Q = model == LBEM_MM ? 50 : 36;
+    const uint32_t Q = uint32_t(model_pops(model));
     const uint32_t cells = kChunkBytes / (storage == LBEM_F32 ? 4u : 2u);
     PopLayout pl{1u, 31u, uint32_t(total), 0};
     if (total > cells) {
@@ -185,7 +185,7 @@ BatchLayout batch_layout(int model, int storage, int32_t n, size_t total) {
 }
 
 lbem_status check_offsets(int32_t model, int32_t storage, int32_t n, const int64_t *offsets) {
-    if (model != LBEM_MM && model != LBEM_HV) return fail(LBEM_EINVAL, "unknown model %d", model);
+    if (model_pops(model) == 0) return fail(LBEM_EINVAL, "unknown model %d", model);
     if (storage < LBEM_F32 || storage > LBEM_F16)
         return fail(LBEM_EINVAL, "storage %d is not available for batches (plain FP32, BF16 or FP16 only)", storage);
     if (n < 1) return fail(LBEM_EINVAL, "need at least one instance");
@@ -299,6 +299,7 @@ void launch_persistent_m(lbem_batch *b, const BatchArgs &a, hipStream_t s) {
 void launch_persistent(lbem_batch *b, int64_t nsteps, hipStream_t s) {
     const BatchArgs a = args_of(b, nsteps);
     if (b->model == LBEM_MM) launch_persistent_m<MM>(b, a, s);
+    else if (b->model == LBEM_MM_DIFF) launch_persistent_m<MMD>(b, a, s);
     else launch_persistent_m<HV>(b, a, s);
 }
 
@@ -434,6 +435,7 @@ static void batch_init_m(lbem_batch *b, const float *E, const float *B) {
 lbem_status lbem_batch_set_fields(lbem_batch *b, const float *E, const float *B) {
     if (!b || !E || !B) return fail(LBEM_EINVAL, "null argument");
     if (b->model == LBEM_MM) batch_init_m<MM>(b, E, B);
+    else if (b->model == LBEM_MM_DIFF) batch_init_m<MMD>(b, E, B);
     else batch_init_m<HV>(b, E, B);
     b->t = 0;
     return hip_check(hipGetLastError(), "init launch");
@@ -509,6 +511,9 @@ lbem_status lbem_batch_step_per_instance(lbem_batch *b, int64_t nsteps) {
             if (b->model == LBEM_MM) {
                 if (odd) launch_one_st<MM, 1>(b, a, s0, L);
                 else launch_one_st<MM, 0>(b, a, s0, L);
+            } else if (b->model == LBEM_MM_DIFF) {
+                if (odd) launch_one_st<MMD, 1>(b, a, s0, L);
+                else launch_one_st<MMD, 0>(b, a, s0, L);
             } else {
                 if (odd) launch_one_st<HV, 1>(b, a, s0, L);
                 else launch_one_st<HV, 0>(b, a, s0, L);
@@ -528,6 +533,9 @@ lbem_status lbem_batch_get_fields(lbem_batch *b, float *E, float *B) {
     if (b->model == LBEM_MM) {
         if (odd) launch_fields_st<MM, 1>(b, a, E, B);
         else launch_fields_st<MM, 0>(b, a, E, B);
+    } else if (b->model == LBEM_MM_DIFF) {
+        if (odd) launch_fields_st<MMD, 1>(b, a, E, B);
+        else launch_fields_st<MMD, 0>(b, a, E, B);
     } else {
         if (odd) launch_fields_st<HV, 1>(b, a, E, B);
         else launch_fields_st<HV, 0>(b, a, E, B);

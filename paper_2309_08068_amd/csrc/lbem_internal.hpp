@@ -30,6 +30,10 @@ inline uint32_t row_block(const lbem_desc *d) {
 
 // Equilibrium-shifted storage formats keep two planes of 16-byte per-cell
 // records (the step at time t reads plane (t + 1) & 1 and writes plane t & 1).
+// Populations per cell of a model, 0 for an unknown model.
+inline int model_pops(int32_t model) {
+    return model == LBEM_MM ? 50 : model == LBEM_HV ? 36 : model == LBEM_MM_DIFF ? 24 : 0;
+}
 inline bool shifted(int32_t storage) { return storage == LBEM_BF16_SHIFTED || storage == LBEM_F16_SHIFTED; }
 // Population layout (see PopLayout): row-form lattices use chunks of a power
 // of two of x-rows with at most kChunkBytes per population plane (measured on
@@ -38,7 +42,7 @@ inline bool shifted(int32_t storage) { return storage == LBEM_BF16_SHIFTED || st
 // in one chunk, and every generic-form lattice, is a single chunk of N cells.
 constexpr uint32_t kChunkBytes = 32768;
 inline PopLayout pop_layout(const lbem_desc *d) {
-    const uint32_t Q = d->model == LBEM_MM ? 50 : 36;
+    const uint32_t Q = uint32_t(model_pops(d->model));
     const uint32_t cells = kChunkBytes / (d->storage == LBEM_F32 ? 4u : 2u);
     const uint64_t rows = uint64_t(d->ny) * d->nz;
     PopLayout L{uint32_t(d->nx), 31u, uint32_t(rows * d->nx), 0};

@@ -323,7 +323,7 @@ bool is_f16(int st) { return st == LBEM_F16 || st == LBEM_F16_SHIFTED; }
 
 lbem_status check_desc(const lbem_desc *d) {
     if (!d) return fail(LBEM_EINVAL, "desc is NULL");
-    if (d->model != LBEM_MM && d->model != LBEM_HV) return fail(LBEM_EINVAL, "unknown model %d", d->model);
+    if (model_pops(d->model) == 0) return fail(LBEM_EINVAL, "unknown model %d", d->model);
     if (d->storage < LBEM_F32 || d->storage > LBEM_F16_SHIFTED)
         return fail(LBEM_EINVAL, "unknown storage %d", d->storage);
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(LBEM_EINVAL, "lattice size must be >= 1 on every axis");
@@ -338,7 +338,6 @@ lbem_status check_desc(const lbem_desc *d) {
     return LBEM_OK;
 }
 
-int model_q(int model) { return model == LBEM_MM ? 50 : 36; }
 size_t storage_bytes(int st) { return st == LBEM_F32 ? 4 : 2; }
 
 }  // namespace
@@ -415,7 +414,7 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     auto *lat = new (std::nothrow) lbem_lattice();
     if (!lat) return fail(LBEM_ENOMEM, "host allocation failed");
     lat->d = *desc;
-    lat->Q = model_q(desc->model);
+    lat->Q = model_pops(desc->model);
     lat->sbytes = storage_bytes(desc->storage);
     lat->N = uint32_t(size_t(desc->nx) * desc->ny * desc->nz);
     lat->bu = row_block(desc) ? row_block(desc) : uint32_t(kBlock);
@@ -515,6 +514,7 @@ static void dispatch_init(lbem_lattice *lat, const float *E, const float *B) {
 lbem_status lbem_set_fields(lbem_lattice *lat, const float *E, const float *B) {
     if (!lat || !E || !B) return fail(LBEM_EINVAL, "null argument");
     if (lat->d.model == LBEM_MM) dispatch_init<MM>(lat, E, B);
+    else if (lat->d.model == LBEM_MM_DIFF) dispatch_init<MMD>(lat, E, B);
     else dispatch_init<HV>(lat, E, B);
     lat->t = 0;
     return hip_check(hipGetLastError(), "init launch");
@@ -755,6 +755,8 @@ static const void *step_kernel_ptr_st(const lbem_lattice *lat, int form) {
 
 static const void *step_kernel_of(const lbem_lattice *lat, int odd, int form) {
     if (lat->d.model == LBEM_MM) return odd ? step_kernel_ptr_st<MM, 1>(lat, form) : step_kernel_ptr_st<MM, 0>(lat, form);
+    if (lat->d.model == LBEM_MM_DIFF)
+        return odd ? step_kernel_ptr_st<MMD, 1>(lat, form) : step_kernel_ptr_st<MMD, 0>(lat, form);
     return odd ? step_kernel_ptr_st<HV, 1>(lat, form) : step_kernel_ptr_st<HV, 0>(lat, form);
 }
 
@@ -921,6 +923,9 @@ static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, floa
     if (lat->d.model == LBEM_MM) {
         if (odd) dispatch_obs_storage<MM, 1>(lat, a);
         else dispatch_obs_storage<MM, 0>(lat, a);
+    } else if (lat->d.model == LBEM_MM_DIFF) {
+        if (odd) dispatch_obs_storage<MMD, 1>(lat, a);
+        else dispatch_obs_storage<MMD, 0>(lat, a);
     } else {
         if (odd) dispatch_obs_storage<HV, 1>(lat, a);
         else dispatch_obs_storage<HV, 0>(lat, a);

@@ -2,6 +2,8 @@
 // Maxwell lattice-Boltzmann schemes, as device code for gfx950.
 //
 // Population numbering (shared by every kernel of this library):
+//   MMD (MM in difference form): q = r * 12 + p * 4 + i for
+//       d^{p(r)}_i = f^{p(r)}_{i0} - f^{p(r)}_{i1} (see MMD below).
 //   MM: q = r * 24 + p * 8 + i * 2 + j for the moving populations f^{p(r)}_{ij}
 //       (r = 0 electric, 1 magnetic; plane p = 0..2; direction i = 0..3 for the
 //       paper's i = 1..4; j = 0, 1), q = 48 and 49 for the rest populations
@@ -64,6 +66,22 @@ struct MM {
     }
 };
 
+// MM in difference form.  Of the MM populations only the differences
+// d^{p(r)}_i = f^{p(r)}_{i0} - f^{p(r)}_{i1} enter D' and B (eq.
+// MacroscopicFieldsMiller, with e_{i1} = -e_{i0} and b_{i1} = -b_{i0}), the two
+// populations of a pair stream along the same v_i, and their equilibria
+// (eq. equilibriumsMiller) differ by 2 u with u = (eps_r/4) E.e_{i0} +
+// B.b_{i0}/(8 mu_r) (r = 0) or E.e_{i0}/4 + B.b_{i0}/8 (r = 1): the current
+// term v.J/16 is common to both and cancels.  So d' = 4 u - d evolves on its
+// own and reproduces E, B, D and H of the 50-population scheme exactly (up to
+// rounding); only the charge density rho_c (the sums and rest populations)
+// is not represented.  24 populations per cell instead of 50.
+struct MMD {
+    static constexpr int Q = 24;
+    __host__ __device__ static constexpr int vel(int q, int a) { return kMMV[(q % 12) / 4][q % 4][a]; }
+    __host__ __device__ static constexpr int opp(int q) { return (q / 12) * 12 + ((q % 12) / 4) * 4 + (q % 4 + 2) % 4; }
+};
+
 // ---------------------------------------------------------------- HV tables
 // Section III velocity set: v1 = +x, v2 = +y, v3 = -x, v4 = -y, v5 = -z, v6 = +z.
 constexpr int kHVV[6][3] = {{1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}, {0, 0, 1}};
@@ -91,7 +109,15 @@ constexpr bool opp_consistent_hv() {
     }
     return true;
 }
-static_assert(opp_consistent_mm() && opp_consistent_hv(), "opposite-direction maps");
+constexpr bool opp_consistent_mmd() {
+    for (int q = 0; q < MMD::Q; ++q) {
+        if (MMD::opp(MMD::opp(q)) != q) return false;
+        for (int a = 0; a < 3; ++a)
+            if (MMD::vel(MMD::opp(q), a) != -MMD::vel(q, a)) return false;
+    }
+    return true;
+}
+static_assert(opp_consistent_mm() && opp_consistent_hv() && opp_consistent_mmd(), "opposite-direction maps");
 
 // ---------------------------------------------------------------- per cell
 // x / d given inv = 1 / d (rounded): one Newton correction of the product makes
@@ -213,6 +239,81 @@ __device__ __forceinline__ void mm_field_equilibrium(float (&f)[50], const CellM
     }
     f[48] = 0.f;
     f[49] = 0.f;
+}
+
+// MM in difference form: the same moments, constitutive relations and u as
+// mm_collide, with d' = 4 u - d (see MMD).
+__device__ __forceinline__ void mmd_collide(float (&d)[24], const CellMedia &m, const float Js[3], CellFields &o) {
+    float D[3] = {0.f, 0.f, 0.f}, B[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        float sb = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float d0 = d[p * 4 + i], d1 = d[12 + p * 4 + i];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (mm_e2(p, i, a) != 0) D[a] += (mm_e2(p, i, a) > 0 ? 0.5f : -0.5f) * d0;
+            sb += d1;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (kMMB[p][a] != 0) B[a] += kMMB[p][a] > 0 ? sb : -sb;
+    }
+    const float den = m.eps_r + 0.5f * m.sigma;
+    const float inv = 1.0f / den;
+    float E[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        E[a] = div_rn(D[a] - 0.5f * Js[a], den, inv);
+        o.E[a] = E[a];
+        o.B[a] = B[a];
+        o.D[a] = m.eps_r * E[a];
+        o.H[a] = 0.5f * (B[a] / m.mu_r);
+    }
+    const float ke0 = 0.25f * m.eps_r, imu = 1.0f / m.mu_r;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        float bb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (kMMB[p][a] != 0) bb += kMMB[p][a] > 0 ? B[a] : -B[a];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float ee = 0.f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (mm_e2(p, i, a) != 0) ee += mm_e2(p, i, a) > 0 ? E[a] : -E[a];
+            ee *= 0.5f;
+            const float u0 = ke0 * ee + 0.125f * div_rn(bb, m.mu_r, imu);
+            const float u1 = 0.25f * ee + 0.125f * bb;
+            d[p * 4 + i] = 4.f * u0 - d[p * 4 + i];
+            d[12 + p * 4 + i] = 4.f * u1 - d[12 + p * 4 + i];
+        }
+    }
+}
+
+// d of the MM equilibrium of given E, B (J = 0): 2 u.
+__device__ __forceinline__ void mmd_field_equilibrium(float (&d)[24], const CellMedia &m, const float E[3],
+                                                      const float B[3]) {
+    const float ke0 = 0.25f * m.eps_r, imu = 1.0f / m.mu_r;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        float bb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (kMMB[p][a] != 0) bb += kMMB[p][a] > 0 ? B[a] : -B[a];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float ee = 0.f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (mm_e2(p, i, a) != 0) ee += mm_e2(p, i, a) > 0 ? E[a] : -E[a];
+            ee *= 0.5f;
+            d[p * 4 + i] = 2.f * (ke0 * ee + 0.125f * div_rn(bb, m.mu_r, imu));
+            d[12 + p * 4 + i] = 2.f * (0.25f * ee + 0.125f * bb);
+        }
+    }
 }
 
 // HV lattice constants: eps0 = mu0 = 3 (vacuum speed 1/3, impedance 1).
@@ -386,6 +487,24 @@ struct Shift<MM> {
     }
 };
 template <>
+struct Shift<MMD> {
+    static constexpr int kNV = 12;  // k = p * 4 + i; populations k, 12 + k
+    __host__ __device__ static constexpr int vel(int k, int a) { return kMMV[k / 4][k % 4][a]; }
+    template <int K>
+    __device__ static void add(float (&f)[24], const Rec &r, float s) {
+        constexpr int p = K / 4, i = K % 4;
+        float ee = 0.f, bb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (mm_e2(p, i, a) != 0) ee += mm_e2(p, i, a) > 0 ? r.E[a] : -r.E[a];
+            if (kMMB[p][a] != 0) bb += kMMB[p][a] > 0 ? r.B[a] : -r.B[a];
+        }
+        // d = 2 u (see Shift<MM>)
+        f[K] += s * (0.25f * r.eps * ee + 0.25f * r.imu * bb);
+        f[12 + K] += s * (0.25f * ee + 0.25f * bb);
+    }
+};
+template <>
 struct Shift<HV> {
     static constexpr int kNV = 6;  // k = i; populations 3i + a, 18 + 3i + a
     __host__ __device__ static constexpr int vel(int k, int a) { return kHVV[k][a]; }
@@ -420,6 +539,15 @@ struct Cell<MM> {
     }
     __device__ static void equilibrium(float (&f)[50], const CellMedia &m, const float E[3], const float B[3]) {
         mm_field_equilibrium(f, m, E, B);
+    }
+};
+template <>
+struct Cell<MMD> {
+    __device__ static void collide(float (&f)[24], const CellMedia &m, const float Js[3], CellFields &o) {
+        mmd_collide(f, m, Js, o);
+    }
+    __device__ static void equilibrium(float (&f)[24], const CellMedia &m, const float E[3], const float B[3]) {
+        mmd_field_equilibrium(f, m, E, B);
     }
 };
 template <>

@@ -16,9 +16,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbem.so")
 
-MODEL = {"mm": 0, "hv": 1}
+MODEL = {"mm": 0, "hv": 1, "mmd": 2}  # "mmd": MM in difference form (24 populations)
 STORAGE = {"f32": 0, "bf16": 1, "f16": 2, "bf16_shifted": 3, "f16_shifted": 4}
-NQ = {"mm": 50, "hv": 36}
+NQ = {"mm": 50, "hv": 36, "mmd": 24}
 STATUS = {0: "LBEM_OK", -1: "LBEM_EINVAL", -2: "LBEM_ENOMEM", -3: "LBEM_EHIP", -4: "LBEM_EUNSTABLE",
           -5: "LBEM_ESTATE", -6: "LBEM_ENOTFINITE"}
 
@@ -423,16 +423,28 @@ class Batch:
         return E, B
 
 
-def batch_from_inputs(bt, storage: str = "f32") -> Batch:
-    """Set up a Batch from an inputs.Batch (media and initial fields)."""
-    b = Batch(bt.model, bt.offsets, bt.eps_r, bt.mu_r, bt.sigma, storage=storage)
+def _model_for(workload_model: str, model: Optional[str]) -> str:
+    # an MM workload (media in MM units) may run on either form of the MM scheme
+    if model is None or model == workload_model:
+        return workload_model
+    if workload_model == "mm" and model == "mmd":
+        return model
+    raise ValueError(f"a {workload_model} workload cannot run on the {model} model")
+
+
+def batch_from_inputs(bt, storage: str = "f32", model: Optional[str] = None) -> Batch:
+    """Set up a Batch from an inputs.Batch (media and initial fields); model
+    "mmd" runs an MM batch in difference form."""
+    b = Batch(_model_for(bt.model, model), bt.offsets, bt.eps_r, bt.mu_r, bt.sigma, storage=storage)
     b.set_fields(bt.E0, bt.B0)
     return b
 
 
-def lattice_from_workload(w, storage: str = "f32", storage_scale: float = 0.0) -> Lattice:
-    """Set up a Lattice from an inputs.Workload (media, fields, sources, probes, detector)."""
-    lat = Lattice(w.model, w.shape, w.eps_r, w.mu_r, w.sigma, storage=storage, storage_scale=storage_scale)
+def lattice_from_workload(w, storage: str = "f32", storage_scale: float = 0.0,
+                          model: Optional[str] = None) -> Lattice:
+    """Set up a Lattice from an inputs.Workload (media, fields, sources, probes,
+    detector); model "mmd" runs an MM workload in difference form."""
+    lat = Lattice(_model_for(w.model, model), w.shape, w.eps_r, w.mu_r, w.sigma, storage=storage, storage_scale=storage_scale)
     lat.set_fields(*w.fields0())
     if w.currents:
         lat.set_currents(w.currents)

@@ -67,6 +67,23 @@ def test_workspace_size_grows_with_model_and_storage(lib):
     assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0 and out.value == n * 50 * 2
 
 
+def test_difference_form_sizes_and_limits(lib):
+    """The MM scheme in difference form keeps 24 populations per cell (in the
+    same chunked layout), runs as a batch, and has no adjoint."""
+    out = C.c_size_t()
+    for shape, storage, size in (((16, 16, 16), "f32", 24 * 4 * 16 ** 3), ((16, 16, 16), "bf16", 24 * 2 * 16 ** 3),
+                                 ((256, 20, 13), "f32", 9 * 24 * 8192 * 4),
+                                 ((16, 16, 16), "bf16_shifted", 24 * 2 * 16 ** 3 + 16 * 16 ** 3)):
+        d = lbem.desc("mmd", shape, storage)
+        assert lib.lbem_state_size(C.byref(d), C.byref(out)) == 0 and out.value == size
+    assert ws("mmd", (16, 16, 16))[1] < ws("mm", (16, 16, 16))[1]
+    off = (C.c_int64 * 3)(0, 10, 30)
+    assert lib.lbem_batch_workspace_size(lbem.MODEL["mmd"], 0, 2, off, C.byref(out)) == 0
+    d = lbem.desc("mmd", (16, 16, 16))
+    assert lib.lbem_adjoint_workspace_size(C.byref(d), 10, 2, 1, C.byref(out)) == -1
+    assert b"adjoint" in lib.lbem_last_error()
+
+
 @pytest.mark.parametrize("storage,q", [("bf16_shifted", 50), ("f16_shifted", 50)])
 def test_shifted_storage_sizes(lib, storage, q):
     """Equilibrium-shifted formats: 16-bit populations plus two planes of

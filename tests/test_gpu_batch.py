@@ -1,7 +1,8 @@
 """GPU parity of the batched ragged 1-D stepper against the FP64 CPU oracle:
 every instance must equal the oracle run of its own 1 x 1 x L lattice, and the
 persistent launch, its HIP graph and the one-launch-per-instance schedule must
-agree bit for bit."""
+agree bit for bit.  The MM scheme in difference form ("mmd") is checked
+against the oracle of the full MM scheme, whose E and B it reproduces."""
 import numpy as np
 import pytest
 import torch
@@ -21,7 +22,7 @@ def rel(a, b):
 
 def oracle_instance(model, eps, mu, sig, E0, B0, steps, real="f64"):
     L = len(eps)
-    P = oracle.Problem(model, (1, 1, L), eps_r=eps, mu_r=mu, sigma=sig)
+    P = oracle.Problem("mm" if model == "mmd" else model, (1, 1, L), eps_r=eps, mu_r=mu, sigma=sig)
     f = oracle.init(P, E0, B0, real=real)
     oracle.run(P, f, 0, steps)
     E, B, _, _ = oracle.fields(P, f, steps)
@@ -36,7 +37,7 @@ def random_batch(seed, lengths):
                 E0=rng.normal(size=(3, tot)), B0=rng.normal(size=(3, tot)))
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", ["mm", "hv", "mmd"])
 @pytest.mark.parametrize("storage", ["f32"])
 def test_batch_random_parity_and_schedules(model, storage):
     lengths = [1, 2, 3, 17, 64, 65, 255, 256, 257, 700, 1031, 5]
@@ -85,15 +86,15 @@ def test_batch_autotune_leaves_state_unchanged():
     assert torch.equal(E0, E1)
 
 
-@pytest.mark.parametrize("model", ["mm"])
+@pytest.mark.parametrize("model", ["mm", "mmd"])
 def test_multilayer_workload_sampled_parity(model):
     """The full multilayer workload (512 instances, lengths 500..8000, 5000
     steps) in the autotuned launch configuration the benchmark times; the
     shortest, the longest and two random instances are compared with the
     oracle run of each instance.  MM only: HV grows an interface mode at
     every layer boundary (see the oracle's spectral test)."""
-    bt = inputs.multilayer(model, steps=5000)
-    b = lbem.batch_from_inputs(bt)
+    bt = inputs.multilayer("mm", steps=5000)
+    b = lbem.batch_from_inputs(bt, model=model)
     b.autotune(10)
     b.step(bt.steps)
     E, B = b.fields()

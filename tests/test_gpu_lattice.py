@@ -4,7 +4,11 @@ Every test drives the HIP library through its C ABI (the ctypes binding) and
 the oracle with the same seeded inputs, then compares the reported fields
 element by element.  FP32 storage must match within 1e-5 relative L2, or --
 where the float32 build of the oracle shows the scheme itself drifts more than
-that in single precision -- within twice that measured float32 floor."""
+that in single precision -- within twice that measured float32 floor.
+
+The MM scheme in difference form ("mmd", 24 populations) is checked against
+the oracle of the full 50-population MM scheme: its E, B, D and H are those of
+MM, so the same bounds apply."""
 import math
 import zlib
 
@@ -18,6 +22,12 @@ from paper_2309_08068_amd import inputs, lbem
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
+MODELS = ["mm", "hv", "mmd"]
+
+
+def base(model):
+    """The scheme whose oracle and workloads a model is checked against."""
+    return "mm" if model == "mmd" else model
 
 
 def rel(a, b):
@@ -67,7 +77,7 @@ def run_gpu(model, shape, p, steps, storage="f32", scale=0.0, probes=None, det_z
 
 
 def run_oracle(model, shape, p, steps, real="f64", probes=None, det_z=None, energy_every=0):
-    P = oracle.Problem(model, shape, eps_r=p["eps"], mu_r=p.get("mu"), sigma=p.get("sig"),
+    P = oracle.Problem(base(model), shape, eps_r=p["eps"], mu_r=p.get("mu"), sigma=p.get("sig"),
                        currents=p.get("currents") or [], plane=p.get("plane"))
     f = oracle.init(P, p["E0"], p["B0"], real=real)
     out = oracle.run(P, f, 0, steps, probes=probes, det_z=det_z, energy_every=energy_every)
@@ -85,7 +95,7 @@ SHAPES = [(1, 1, 17), (7, 5, 9), (16, 16, 16), (33, 3, 5), (300, 1, 1), (1, 40, 
           (128, 9, 60), (256, 20, 13), (384, 10, 13), (512, 3, 45)]
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("steps", [8, 9])
 def test_random_state_parity(model, shape, steps):
@@ -100,7 +110,7 @@ def test_random_state_parity(model, shape, steps):
         assert rel(g[k], o[k]) < TOL, (k, rel(g[k], o[k]))
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("shape", [(9, 7, 11), (128, 5, 40)])
 def test_point_currents_with_own_period_and_phase(model, shape):
     """Soft point currents added one by one (lbem_add_point_current), each with
@@ -131,7 +141,7 @@ def test_point_currents_with_own_period_and_phase(model, shape):
 SHIFTED_BOUND = {"bf16_shifted": 2e-2, "f16_shifted": 3e-3}
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("steps", [8, 9])
 @pytest.mark.parametrize("storage", ["bf16_shifted", "f16_shifted"])
@@ -146,14 +156,14 @@ def test_shifted_storage_random_state(model, shape, steps, storage):
         assert rel(g[k], o[k]) < SHIFTED_BOUND[storage], (k, rel(g[k], o[k]))
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("plain,shifted,scale", [("bf16", "bf16_shifted", 0.0), ("f16", "f16_shifted", 256.0)])
 def test_shifted_storage_beats_plain_on_smooth_fields(model, plain, shifted, scale):
     """On a smooth 3-D wave the stored non-equilibrium remainder is a small part
     of each population, so the shifted format's error against the FP64 oracle
     must be at most half that of the plain format (generic and row form)."""
     for shape in ((32, 32, 32), (128, 8, 32)):
-        c = inputs.VACUUM_SPEED[model]
+        c = inputs.VACUUM_SPEED[base(model)]
         E0, B0 = inputs.gaussian_pulse(shape, 12.0, 4.0, c)
         p = dict(eps=np.full(int(np.prod(shape)), 1.5), mu=None, sig=None, E0=E0, B0=B0)
         o = run_oracle(model, shape, p, 100)
@@ -165,7 +175,7 @@ def test_shifted_storage_beats_plain_on_smooth_fields(model, plain, shifted, sca
             assert es < 0.5 * ep, (shape, k, ep, es)
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("shape,tuning", [((12, 10, 14), None), ((128, 6, 14), None), ((128, 9, 60), None),
                                           ((384, 3, 14), ((3, 7), (0, 2))), ((256, 4, 14), ((2, 3), (2, 0)))])
 def test_observations_parity(model, shape, tuning):
@@ -183,14 +193,13 @@ def test_observations_parity(model, shape, tuning):
     np.testing.assert_allclose(g["detector"][0], o["detector"].sum(), rtol=TOL)
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("shape", [(6, 7, 8), (128, 3, 4)])
 def test_energy_call_matches_oracle(model, shape):
     p = random_problem(model, shape, seed=11)
     _, lat = run_gpu(model, shape, p, 5)
     u = lat.energy().item()
     o = run_oracle(model, shape, p, 5)
-    P = oracle.Problem(model, shape, eps_r=p["eps"], mu_r=p["mu"], sigma=p["sig"])
     uo = 0.5 * ((o["E"] * o["D"]).sum() + (o["B"] * o["H"]).sum())
     assert abs(u - uo) <= TOL * abs(uo)
 
@@ -201,14 +210,14 @@ def float_floor(model, shape, p, steps):
     return max(rel(o32[k], o64[k]) for k in "EB"), o64
 
 
-@pytest.mark.parametrize("model,steps", [("mm", 2000), ("hv", 1000)])
+@pytest.mark.parametrize("model,steps", [("mm", 2000), ("hv", 1000), ("mmd", 2000)])
 def test_interface_workload_parity(model, steps):
     """1 x 1 x 1000 Gaussian pulse across eps_r 1 -> 2.5.  MM for the full 2000
     steps.  The modified HV model has a growing mode at dielectric interfaces
     (about one e-fold per 260 steps at this contrast, see the oracle's spectral
     test), which amplifies any single-precision rounding by ~2000x over 2000
     steps, so HV is compared over the first 1000 steps."""
-    w = inputs.interface(model, steps=steps)
+    w = inputs.interface(base(model), steps=steps)
     p = dict(eps=w.eps_r, mu=w.mu_r, sig=None, E0=w.E0, B0=w.B0)
     floor, o = float_floor(model, w.shape, p, w.steps)
     g, _ = run_gpu(model, w.shape, p, w.steps)
@@ -220,10 +229,10 @@ def test_interface_workload_parity(model, steps):
         assert errs[k] < tol, (k, errs[k])
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 def test_skin_workload_parity(model):
     """1 x 1 x 4096 hard-source plane wave into a conductor, 20000 steps."""
-    w = inputs.skin(model)
+    w = inputs.skin(base(model))
     E0, B0 = w.fields0()
     p = dict(eps=None, mu=None, sig=w.sigma, E0=E0, B0=B0, plane=w.plane)
     floor, o = float_floor(model, w.shape, p, w.steps)
@@ -248,14 +257,14 @@ def dipole_oracle():
     return get
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("storage,tol", [("f32", TOL), ("bf16_shifted", 1e-2)])
 def test_dipole_full_size_parity(dipole_oracle, model, storage, tol):
     """The 256^3 dipole workload (vacuum, 16-cell sponge, point current at the
     centre) in the launch configuration the benchmark times (after its
     autotuner), for 8 steps against the oracle on the full lattice."""
-    w, p, o = dipole_oracle(model)
-    lat = lbem.lattice_from_workload(w, storage=storage)
+    w, p, o = dipole_oracle(base(model))
+    lat = lbem.lattice_from_workload(w, storage=storage, model=model)
     lat.autotune(2)
     series = lat.set_probes(w.probes, w.steps)
     lat.step(w.steps)
@@ -266,13 +275,13 @@ def test_dipole_full_size_parity(dipole_oracle, model, storage, tol):
         assert rel(g[k], o[k]) < tol, (k, rel(g[k], o[k]))
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 def test_dipole_light_cone_and_symmetry_long_run(model):
     """Properties that hold at any size, on the full 256^3 dipole run of 1000
     steps: the fields stay finite, and a point current along z at the centre
     radiates symmetrically under x <-> y exchange about the source."""
-    w = inputs.dipole(model, n=256, steps=1000)
-    lat = lbem.lattice_from_workload(w)
+    w = inputs.dipole(base(model), n=256, steps=1000)
+    lat = lbem.lattice_from_workload(w, model=model)
     lat.step(w.steps)
     E, B, _, _ = lat.fields()
     E = E.reshape(3, 256, 256, 256)
@@ -290,8 +299,8 @@ def dipole384_f32():
 
     def get(model, steps):
         if (model, steps) not in cache:
-            w = inputs.dipole(model, n=384, steps=steps)
-            lat = lbem.lattice_from_workload(w)
+            w = inputs.dipole(base(model), n=384, steps=steps)
+            lat = lbem.lattice_from_workload(w, model=model)
             lat.autotune(2)
             lat.step(steps)
             E, B, _, _ = lat.fields()
@@ -305,7 +314,7 @@ def dipole384_f32():
 DIPOLE384_BOUND = {"f32": 0.0, "bf16": 0.1, "f16": 0.02, "bf16_shifted": 0.1, "f16_shifted": 0.02}
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "bf16_shifted", "f16_shifted"])
 def test_dipole_384_properties(dipole384_f32, model, storage):
     """The 384^3 dipole of the precision sweep, at full size in the benchmark's
@@ -316,8 +325,9 @@ def test_dipole_384_properties(dipole384_f32, model, storage):
     the centre; and, for the 16-bit formats, the stated bound on the distance
     from the FP32-storage run.  The FP64 oracle at this size would hold 45 GB."""
     steps, n, c = 150, 384, 192
-    w = inputs.dipole(model, n=n, steps=steps)
-    lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=1024.0 if "f16" in storage else 0.0)
+    w = inputs.dipole(base(model), n=n, steps=steps)
+    lat = lbem.lattice_from_workload(w, storage=storage, storage_scale=1024.0 if "f16" in storage else 0.0,
+                                     model=model)
     lat.autotune(2)
     lat.step(steps)
     E, B, _, _ = lat.fields()
@@ -342,7 +352,7 @@ def test_dipole_384_properties(dipole384_f32, model, storage):
         assert dE < DIPOLE384_BOUND[storage] and dB < DIPOLE384_BOUND[storage]
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("shape", [(10, 9, 8), (128, 4, 5), (256, 20, 13)])
 @pytest.mark.parametrize("storage", ["f32", "bf16_shifted"])
 def test_save_load_and_determinism(model, shape, storage):
@@ -368,7 +378,7 @@ def test_save_load_and_determinism(model, shape, storage):
     assert lat.energy().item() == lat2.energy().item()
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("storage,bound", [("bf16", 2e-2), ("f16", 3e-3)])
 def test_low_precision_storage_bound(model, storage, bound):
     """BF16 / FP16 population storage with FP32 collision: the error against the
@@ -376,7 +386,7 @@ def test_low_precision_storage_bound(model, storage, bound):
     parity is expected; the bound is a property of the format), in the generic
     and the row form."""
     for shape in ((32, 32, 32), (128, 8, 32)):
-        c = inputs.VACUUM_SPEED[model]
+        c = inputs.VACUUM_SPEED[base(model)]
         E0, B0 = inputs.gaussian_pulse(shape, 12.0, 4.0, c)
         p = dict(eps=np.full(int(np.prod(shape)), 1.5), mu=None, sig=None, E0=E0, B0=B0)
         g, _ = run_gpu(model, shape, p, 100, storage=storage, scale=256.0 if storage == "f16" else 0.0)
@@ -411,7 +421,7 @@ def test_unstable_and_invalid_media_rejected():
 
 
 @pytest.mark.parametrize("model,storage", [("mm", "f32"), ("mm", "bf16"), ("hv", "f32"), ("mm", "bf16_shifted"),
-                                           ("hv", "f16_shifted")])
+                                           ("hv", "f16_shifted"), ("mmd", "f32"), ("mmd", "bf16_shifted")])
 def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage):
     """Every (address form, blocks-per-CU cap) choice of the step kernel gives
     the same bits; autotune leaves the state as it found it."""
