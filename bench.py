@@ -155,8 +155,8 @@ def time_adjoint(model: str, steps: int, K: int, keep: int):
     import torch
     from paper_2309_08068_amd import inputs, lbem
 
-    w = inputs.slab(model, steps=steps)
-    lat = lbem.lattice_from_workload(w)
+    w = inputs.slab(workload_model(model), steps=steps)
+    lat = lbem.lattice_from_workload(w, model=model)
     lat.autotune(5)
     lat.step(5)
     # a short adjoint pass lets the library pick its adjoint launch tuning
@@ -343,6 +343,7 @@ def main():
         # The headline ratio is the 10-segment schedule, sized for 288 GB parts.
         runs = [time_adjoint("hv", args.adjoint_steps, 50, k) for k in (1, 10, 30)]
         runs.append(time_adjoint("mm", args.adjoint_steps, 50, 1))
+        runs.append(time_adjoint("mmd", args.adjoint_steps, 50, 1))
         line["adjoint"] = runs
         line["adjoint_over_forward"] = runs[1]["ratio"]
         for r in runs:

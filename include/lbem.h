@@ -17,7 +17,7 @@
  *            term free of J, so d' = 2 d_eq - d evolves on its own and gives
  *            the E, B, D, H of LBEM_MM (equal up to FP32 rounding) at 24 / 50
  *            of its traffic.  The charge density of the sums and rest
- *            populations is not represented.  No adjoint (use LBEM_MM).
+ *            populations is not represented.
  * One time step (Appendix B) = collision with tau = 1/2 (moments, constitutive
  * relations and current, equilibria, f' = 2 f_eq - f [+ T]), imposition of hard
  * sources, advection f(x + v_q) <- f'(x).  All boundaries are periodic.
@@ -245,8 +245,8 @@ lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t);
  * recomputes each segment storing E(f_n) per step (FP32 frames), then runs
  * the segment's adjoint steps in reverse (in-place AA streaming with reversed
  * velocities).  Gradients accumulate in FP32 over a segment and in FP64
- * across segments.  LBEM_MM and LBEM_HV (LBEM_MM_DIFF: LBEM_EINVAL); no soft
- * or hard sources may be set.
+ * across segments.  Every model (LBEM_MM_DIFF gives the gradients of LBEM_MM
+ * at 24 / 50 of the traffic); no soft or hard sources may be set.
  * ------------------------------------------------------------------------ */
 
 /* Bytes of adjoint workspace for nsteps steps with a checkpoint every K steps,

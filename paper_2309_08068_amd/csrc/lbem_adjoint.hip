@@ -36,6 +36,13 @@ struct MMRev {
     __host__ __device__ static constexpr int opp(int q) { return MM::opp(q); }
 };
 
+// MM in difference form with every velocity reversed.
+struct MMDRev {
+    static constexpr int Q = 24;
+    __host__ __device__ static constexpr int vel(int q, int a) { return -MMD::vel(q, a); }
+    __host__ __device__ static constexpr int opp(int q) { return MMD::opp(q); }
+};
+
 // HV with every velocity reversed.
 struct HVRev {
     static constexpr int Q = 36;
@@ -231,6 +238,96 @@ struct AdjCell<MM> {
         mm_adjoint_cell(mu, E, m, plane, first, E0c, gE, gS);
     }
 };
+// MM in difference form: the collision d' = 4 u(E(d), B(d)) - d is linear in
+// d; with adjoint moments Me_r = sum_i e_{i0} mu^(r)_i and Mb_r = sum_i b_{i0}
+// mu^(r)_i (E = D'/a, a = eps_r + sigma/2) its transpose is
+//   lambda^(0)_i = e_{i0} . (eps_r Me_0 + Me_1) / a - mu^(0)_i,
+//   lambda^(1)_i = b_{i0} . (Mb_0 / (2 mu_r) + Mb_1 / 2) - mu^(1)_i,
+// and mu . d' depends on theta through E only.  The sums f_{i0} + f_{i1} of
+// the full scheme never reach E, so their adjoint is zero and this is the MM
+// adjoint restricted to the differences.
+__device__ __forceinline__ void mmd_adjoint_cell(float (&mu)[24], const float E[3], const CellMedia &m, bool plane,
+                                                 bool first, const float (&E0c)[3], float &gE, float &gS) {
+    const float a = m.eps_r + 0.5f * m.sigma;
+    const float ia = 1.0f / a;
+    float Me0[3] = {0.f, 0.f, 0.f}, Me1[3] = {0.f, 0.f, 0.f}, Mb0[3] = {0.f, 0.f, 0.f}, Mb1[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float d0 = mu[p * 4 + i], d1 = mu[12 + p * 4 + i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (mm_e2(p, i, c) != 0) {
+                    Me0[c] += (mm_e2(p, i, c) > 0 ? 0.5f : -0.5f) * d0;
+                    Me1[c] += (mm_e2(p, i, c) > 0 ? 0.5f : -0.5f) * d1;
+                }
+                if (kMMB[p][c] != 0) {
+                    Mb0[c] += kMMB[p][c] > 0 ? d0 : -d0;
+                    Mb1[c] += kMMB[p][c] > 0 ? d1 : -d1;
+                }
+            }
+        }
+    float Me0E = 0.f, Me1E = 0.f, E2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Me0E += Me0[c] * E[c];
+        Me1E += Me1[c] * E[c];
+        E2 += E[c] * E[c];
+    }
+    // d/d eps_r: dE = -E/a; d/d sigma: dE = -E/(2a)
+    gE = ia * (0.5f * m.sigma * Me0E - Me1E);
+    gS = -0.5f * ia * (m.eps_r * Me0E + Me1E);
+    if (plane) {
+        gE -= 2.f * E2 * ia;
+        gS -= E2 * ia;
+    }
+    float GD[3], GB[3], LD[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        GD[c] = ia * (m.eps_r * Me0[c] + Me1[c]);
+        GB[c] = Mb0[c] * (0.5f / m.mu_r) + 0.5f * Mb1[c];
+        LD[c] = plane ? 2.f * E[c] * ia : 0.f;  // dl/dD' = 2 E / a
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        float gb = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (kMMB[p][c] != 0) gb += kMMB[p][c] > 0 ? GB[c] : -GB[c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float ge = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (mm_e2(p, i, c) != 0) ge += mm_e2(p, i, c) > 0 ? GD[c] + LD[c] : -(GD[c] + LD[c]);
+            mu[p * 4 + i] = 0.5f * ge - mu[p * 4 + i];
+            mu[12 + p * 4 + i] = gb - mu[12 + p * 4 + i];
+        }
+    }
+    if (first) {
+        // d_0 = 2 u(E0, B0): d d^(0)_i / d eps_r = E0 . e_{i0} / 2
+        float Le0[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (mm_e2(p, i, c) != 0) Le0[c] += (mm_e2(p, i, c) > 0 ? 0.5f : -0.5f) * mu[p * 4 + i];
+        gE += 0.5f * (E0c[0] * Le0[0] + E0c[1] * Le0[1] + E0c[2] * Le0[2]);
+    }
+}
+
+template <>
+struct AdjCell<MMD> {
+    using Rev = MMDRev;
+    __device__ static void step(float (&mu)[24], const float E[3], const CellMedia &m, bool plane, bool first,
+                                const float (&E0c)[3], float &gE, float &gS) {
+        mmd_adjoint_cell(mu, E, m, plane, first, E0c, gE, gS);
+    }
+};
+
 template <>
 struct AdjCell<HV> {
     using Rev = HVRev;
@@ -363,6 +460,7 @@ const void *adjoint_ptr_p(uint32_t rb, int form) {
 const void *adjoint_ptr(const lbem_lattice *lat, int odd, int form) {
     const uint32_t rb = row_block(&lat->d);
     if (lat->d.model == LBEM_MM) return odd ? adjoint_ptr_p<MM, 1>(rb, form) : adjoint_ptr_p<MM, 0>(rb, form);
+    if (lat->d.model == LBEM_MM_DIFF) return odd ? adjoint_ptr_p<MMD, 1>(rb, form) : adjoint_ptr_p<MMD, 0>(rb, form);
     return odd ? adjoint_ptr_p<HV, 1>(rb, form) : adjoint_ptr_p<HV, 0>(rb, form);
 }
 
@@ -422,7 +520,6 @@ lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, i
     lbem_status st = lbem_workspace_size(desc, &dummy);
     if (st) return st;
     if (!bytes) return fail(LBEM_EINVAL, "bytes is NULL");
-    if (desc->model == LBEM_MM_DIFF) return fail(LBEM_EINVAL, "the adjoint is provided for LBEM_MM and LBEM_HV");
     if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
     *bytes = adj_layout(desc, nsteps, K, keep).total;
     return LBEM_OK;
@@ -431,7 +528,6 @@ lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, i
 lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z, void *ws,
                                  size_t ws_bytes, double *loss) {
     if (!lat || !ws || !loss) return fail(LBEM_EINVAL, "null argument");
-    if (lat->d.model == LBEM_MM_DIFF) return fail(LBEM_EINVAL, "the adjoint is provided for LBEM_MM and LBEM_HV");
     if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
     if (lat->nsrc > 0 || lat->plane_z >= 0) return fail(LBEM_ESTATE, "the adjoint needs a lattice without sources");
     if (det_z < 0 || det_z >= lat->d.nz) return fail(LBEM_EINVAL, "detector plane z = %d outside the lattice", det_z);

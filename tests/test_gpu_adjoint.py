@@ -1,6 +1,7 @@
 """GPU adjoint (hand-written reverse-time kernels behind a torch.autograd.Function)
 against the FP64 automatic-differentiation reference and against central finite
-differences of the GPU's own forward loss."""
+differences of the GPU's own forward loss.  The MM scheme in difference form
+("mmd") has the loss, and so the gradients, of the full MM scheme."""
 import numpy as np
 import pytest
 import torch
@@ -37,7 +38,7 @@ def autodiff(shape, d, nsteps, det_z, model="mm"):
     T = lambda a: torch.tensor(a.reshape(-1, nz, ny, nx) if a.ndim == 2 else a.reshape(nz, ny, nx))
     eps = T(d["eps"]).requires_grad_(True)
     sig = T(d["sig"]).requires_grad_(True)
-    loss = tr.detector_loss if model == "mm" else tr.hv_detector_loss
+    loss = tr.hv_detector_loss if model == "hv" else tr.detector_loss
     L, _ = loss(eps, sig, T(d["mu"]), T(d["E0"]), T(d["B0"]), nsteps, det_z)
     ge, gs = torch.autograd.grad(L, (eps, sig))
     return L.item(), ge.numpy().reshape(-1), gs.numpy().reshape(-1)
@@ -55,7 +56,7 @@ def gpu_grad(shape, d, nsteps, det_z, K, model="mm", keep=1):
     return L.item(), eps.grad.cpu().numpy(), sig.grad.cpu().numpy()
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", ["mm", "hv", "mmd"])
 @pytest.mark.parametrize("shape,nsteps,K,keep", [((6, 5, 16), 40, 7, 1), ((6, 5, 16), 41, 41, 1),
                                                  ((6, 5, 16), 40, 7, 3), ((6, 5, 16), 40, 7, 6),
                                                  ((128, 2, 12), 25, 4, 2), ((256, 1, 6), 17, 5, 1),
@@ -89,7 +90,7 @@ def test_adjoint_leaves_forward_state():
     assert torch.equal(lat.fields()[0], E1)
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", ["mm", "hv", "mmd"])
 def test_one_call_adjoint_equals_two_passes(model):
     """lbem_adjoint gives the bits of lbem_adjoint_forward + lbem_adjoint_backward."""
     shape = (128, 3, 12)
@@ -109,7 +110,7 @@ def test_one_call_adjoint_equals_two_passes(model):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("model", ["hv", "mm"])
+@pytest.mark.parametrize("model", ["hv", "mm", "mmd"])
 def test_adjoint_launch_forms_are_bit_identical(model):
     """Every launch form of the adjoint kernel (LDS x-shifts with early or late
     store addresses, direct addressing), per parity, gives the same bits, twice
@@ -150,13 +151,17 @@ def test_adjoint_rejects_sources_and_bad_arguments():
         lat2.adjoint_backward(ws)
 
 
+def base(model):
+    return "mm" if model == "mmd" else model
+
+
 def oracle_loss(model, shape, eps, sig, E0, B0, nsteps, det_z):
-    P = oracle.Problem(model, shape, eps_r=eps, sigma=sig)
+    P = oracle.Problem(base(model), shape, eps_r=eps, sigma=sig)
     f = oracle.init(P, E0, B0)
     return oracle.run(P, f, 0, nsteps, det_z=det_z)["detector"].sum()
 
 
-@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("model", ["mm", "hv", "mmd"])
 def test_inverse_design_gradient_finite_differences(model):
     """The inverse-design lattice (smooth random eps_r in [1, 4] and sigma in
     [0, 0.02] over a tapered slab, plane-wave pulse, detector plane,
@@ -164,7 +169,7 @@ def test_inverse_design_gradient_finite_differences(model):
     directional derivatives against central finite differences of the FP64
     oracle's loss (the GPU's own FP32 loss is too noisy for a 1e-3 check at a
     usable step; its loss is compared with the oracle's instead)."""
-    w = inputs.slab(model, shape=(32, 32, 128), slab_z=(48, 80), pulse_z=28.0, pulse_width=6.0, det_z=112,
+    w = inputs.slab(base(model), shape=(32, 32, 128), slab_z=(48, 80), pulse_z=28.0, pulse_width=6.0, det_z=112,
                     sponge=8, steps=600, seed=0)
     shape = w.shape
     E0, B0 = w.fields0()

@@ -35,7 +35,7 @@ def odd_lds_kernels(src, tmp_path):
         yield name, ops
 
 
-@pytest.mark.parametrize("src,expect", [("lbem_lattice.hip", 120), ("lbem_adjoint.hip", 16)])
+@pytest.mark.parametrize("src,expect", [("lbem_lattice.hip", 120), ("lbem_adjoint.hip", 24)])
 def test_lds_reads_and_writes_stay_in_their_phase(src, expect, tmp_path):
     n = 0
     for name, ops in odd_lds_kernels(src, tmp_path):
