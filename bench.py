@@ -10,7 +10,8 @@ model with FP32 population storage; the HV model, BF16 storage, the
 equilibrium-shifted BF16 storage and the MM scheme in difference form (24
 populations per cell, same E and B) are timed the same way and reported under
 "variants".  Further sections: the batched ragged 1-D multilayer workload, the
-adjoint on the 128 x 128 x 256 inverse-design lattice, the 384^3 precision
+adjoint on the 128 x 128 x 256 inverse-design lattice, the radiation pattern of
+the Gaussian dipole at 256^3 (flux monitor), the 384^3 precision
 sweep, and the FP64 oracle on the host cores.
 
 Prints one JSON line.  `value` is lattice updates per second (MLUPS) with the
@@ -187,6 +188,42 @@ def time_adjoint(model: str, steps: int, K: int, keep: int):
             "adjoint_total_s": round(adj, 4), "ratio": round(adj / fwd, 3), "finite_gradients": ok}
 
 
+def radiation_pattern(model: str, n: int):
+    """Section IV-C radiation pattern at n^3: Gaussian dipole, flux monitor on a
+    sphere of radius R; deviation of the normalised r^2 max|E x H| from
+    sin^2(theta), and the equatorial flux over the Hertz-dipole value."""
+    import math
+
+    import numpy as np
+    import torch
+    from paper_2309_08068_amd import inputs, lbem
+
+    rad = inputs.radiation(workload_model(model), n=n)
+    w = rad.workload
+    lat = lbem.lattice_from_workload(w, model=model)
+    lat.autotune(2)
+    flux = lat.set_flux_monitor(rad.cells, *rad.window)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(w.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    smax = flux.cpu().numpy() * rad.radius ** 2
+    pattern = smax / smax.max()
+    om = 2 * math.pi / rad.period
+    pm = sum(c[1][2] for c in w.currents) / om
+    wm = workload_model(model)
+    theory = inputs.VACUUM_CONSTANTS[wm][1] * om ** 4 * pm ** 2 / (16 * math.pi ** 2 * inputs.VACUUM_SPEED[wm])
+    eq = np.abs(rad.theta - math.pi / 2) < 0.3
+    ratio = smax[eq] / (theory * np.sin(rad.theta[eq]) ** 2)
+    del lat
+    torch.cuda.empty_cache()
+    return {"workload": f"radiation_{n}^3_{model}", "steps": w.steps, "sample_radius": round(float(rad.radius.mean()), 2),
+            "wavelength": round(rad.wavelength, 2), "samples": len(rad.cells), "run_s": round(wall, 4),
+            "pattern_max_dev_from_sin2": round(float(np.abs(pattern - np.sin(rad.theta) ** 2).max()), 4),
+            "equatorial_flux_over_theory": [round(float(ratio.min()), 3), round(float(ratio.max()), 3)]}
+
+
 def time_precision(model: str, n: int, steps: int):
     """Precision sweep on the n^3 point dipole: every storage format runs the
     same `steps` steps (after the autotuner); reports its throughput and the
@@ -253,6 +290,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=1500)
     ap.add_argument("--no-sweep", action="store_true", help="skip the 384^3 precision sweep")
+    ap.add_argument("--no-radiation", action="store_true", help="skip the 256^3 radiation-pattern runs")
     ap.add_argument("--sweep-n", type=int, default=384)
     ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--profile", action="store_true",
@@ -348,6 +386,10 @@ def main():
         line["adjoint_over_forward"] = runs[1]["ratio"]
         for r in runs:
             print(f"# adjoint: {r}", file=sys.stderr, flush=True)
+    if not args.no_radiation:
+        line["radiation_pattern"] = [radiation_pattern(m, args.n) for m in ("mm", "hv", "mmd")]
+        for r in line["radiation_pattern"]:
+            print(f"# radiation: {r}", file=sys.stderr, flush=True)
     if not args.no_sweep:
         line["precision_sweep"] = [time_precision(m, args.sweep_n, args.sweep_steps) for m in ("mm", "hv")]
     if not args.no_cpu_baseline:

@@ -96,6 +96,7 @@ typedef struct lbem_lattice lbem_lattice;
 /* Limits of the per-lattice tables held in the workspace. */
 #define LBEM_MAX_SOURCES 65536
 #define LBEM_MAX_PROBES 4096
+#define LBEM_MAX_FLUX_CELLS 65536
 
 /* Library version as major * 10000 + minor * 100 + patch. */
 int32_t lbem_version(void);
@@ -172,6 +173,18 @@ lbem_status lbem_set_plane_source(lbem_lattice *lat, int32_t z, const float *E0,
  * cells: host int64 [n]; series: dev double [cap_rows][n][6].  n = 0 disables.
  * Synchronises the stream. */
 lbem_status lbem_set_probes(lbem_lattice *lat, int32_t n, const int64_t *cells, int64_t cap_rows, double *series);
+
+/* Energy-flux monitor for radiation patterns (Section IV-C: the largest
+ * energy flux over one period at points of a sphere around a dipole): every
+ * later step whose time level n (the level of the state it collides) lies in
+ * [n_begin, n_end) first sets maxflux[k] = max(maxflux[k], |E x H|) with E and
+ * H the fields reported at level n in cell cells[k] (FP64 product of the FP32
+ * fields).  cells: host int64 [n], n <= LBEM_MAX_FLUX_CELLS, each in [0, N);
+ * maxflux: dev double [n], owned by the caller, who initialises it (zeros)
+ * and keeps it alive while the monitor is set; the library only folds into
+ * it.  n = 0 disables.  Synchronises the stream. */
+lbem_status lbem_set_flux_monitor(lbem_lattice *lat, int32_t n, const int64_t *cells, int64_t n_begin, int64_t n_end,
+                                  double *maxflux);
 
 /* Detector plane z (z < 0 disables): every later step adds the sum over the
  * plane of |E|^2 of the state it collides to an FP64 accumulator kept in the

@@ -14,7 +14,7 @@ namespace lbem {
 
 // Byte offsets of the regions of a lattice workspace.
 struct WsLayout {
-    size_t pop, rec, eps, mu, sig, en_part, det_part, src_blk, src_cell, src_J0, src_tp, prb_blk, prb_cell, prb_slot,
+    size_t pop, rec, eps, mu, sig, en_part, det_part, src_blk, src_cell, src_J0, src_tp, prb_blk, prb_cell, prb_slot, flx_cell,
         flags;
     size_t det_cap;  // detector partial slots
     size_t total;
@@ -141,6 +141,10 @@ struct lbem_lattice {
     int32_t nprobe;
     int64_t prb_cap, prb_t0;
     double *prb_series;
+    // energy-flux monitor
+    int32_t flx_n;
+    int64_t flx_t0, flx_t1;
+    double *flx_max;
     // detector
     int32_t det_z;
     uint32_t det_b0, det_b1;

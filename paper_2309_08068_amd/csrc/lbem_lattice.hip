@@ -209,18 +209,12 @@ struct ObsArgs {
     const void *rec;  // shifted storage: the record plane this state's reader uses
 };
 
-// Reported fields of the current state (no update).
+// Reported fields of cell cc of the current state.
 template <class M, int ODD, class ST>
-__global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
-    __shared__ double sm_en[4];
-    const uint32_t blk = blockIdx.x;
-    const uint32_t c = blk * kBlock + threadIdx.x;
-    const bool live = c < a.N;
-    const uint32_t cc = live ? c : a.N - 1;
+__device__ __forceinline__ void observe_cell(const ObsArgs &a, uint32_t cc, CellFields &o) {
     const uint32_t nxy = a.nx * a.ny;
     const uint32_t z = cc / nxy, rem = cc - z * nxy, y = rem / a.nx, x = rem - y * a.nx;
     const Nbr nb = make_nbr(cc, x, y, z, a.nx, a.ny, a.nz);
-    const size_t N = a.N;
     float f[M::Q];
     gather_any<M, ODD, ST>(static_cast<const typename ST::T *>(a.pop), a.pl, nb, f, a.inv_scale);
     if constexpr (ST::kShift)
@@ -231,15 +225,26 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
         const uint32_t u = cc / a.bu;
         const int s0 = a.src_blk[u], s1 = a.src_blk[u + 1];
         for (int k = s0; k < s1; ++k)
-            if (a.src_cell[k] == int32_t(c)) {
+            if (a.src_cell[k] == int32_t(cc)) {
                 const float w = source_weight_dev(a.src_t, a.src_tp[2 * k], a.src_tp[2 * k + 1]);
                 Js[0] = a.src_J0[3 * k] * w;
                 Js[1] = a.src_J0[3 * k + 1] * w;
                 Js[2] = a.src_J0[3 * k + 2] * w;
             }
     }
-    CellFields o;
     Cell<M>::collide(f, m, Js, o);
+}
+
+// Reported fields of the current state (no update).
+template <class M, int ODD, class ST>
+__global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
+    __shared__ double sm_en[4];
+    const uint32_t blk = blockIdx.x;
+    const uint32_t c = blk * kBlock + threadIdx.x;
+    const bool live = c < a.N;
+    const size_t N = a.N;
+    CellFields o;
+    observe_cell<M, ODD, ST>(a, live ? c : a.N - 1, o);
     if (live) {
         for (int d = 0; d < 3; ++d) {
             if (a.E) a.E[d * N + c] = o.E[d];
@@ -255,6 +260,20 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(ObsArgs a) {
         const double s = block_sum(u, sm_en);
         if (threadIdx.x == 0) a.en_part[blk] = s;
     }
+}
+
+// Energy-flux monitor: maxflux[k] = max(maxflux[k], |E x H|) of the reported
+// fields in cells[k] (one thread per monitored cell).
+template <class M, int ODD, class ST>
+__global__ __launch_bounds__(kBlock) void flux_kernel(ObsArgs a, const int32_t *cells, uint32_t n, double *maxflux) {
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    CellFields o;
+    observe_cell<M, ODD, ST>(a, uint32_t(cells[k]), o);
+    const double Sx = double(o.E[1]) * o.H[2] - double(o.E[2]) * o.H[1];
+    const double Sy = double(o.E[2]) * o.H[0] - double(o.E[0]) * o.H[2];
+    const double Sz = double(o.E[0]) * o.H[1] - double(o.E[1]) * o.H[0];
+    maxflux[k] = fmax(maxflux[k], sqrt(Sx * Sx + Sy * Sy + Sz * Sz));
 }
 
 // f := f_eq(E, B, J = 0) in natural layout.  Shifted storage: slot (q, c)
@@ -371,6 +390,7 @@ WsLayout layout(const lbem_desc *d) {
     L.prb_blk = take((nblocks + 1) * 4);
     L.prb_cell = take(size_t(LBEM_MAX_PROBES) * 4);
     L.prb_slot = take(size_t(LBEM_MAX_PROBES) * 4);
+    L.flx_cell = take(size_t(LBEM_MAX_FLUX_CELLS) * 4);
     L.flags = take(64);
     L.total = off;
     return L;
@@ -673,6 +693,33 @@ lbem_status lbem_set_probes(lbem_lattice *lat, int32_t n, const int64_t *cells, 
     return LBEM_OK;
 }
 
+lbem_status lbem_set_flux_monitor(lbem_lattice *lat, int32_t n, const int64_t *cells, int64_t n_begin, int64_t n_end,
+                                  double *maxflux) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (n < 0 || n > LBEM_MAX_FLUX_CELLS)
+        return fail(LBEM_EINVAL, "flux-monitor cell count %d outside [0, %d]", n, LBEM_MAX_FLUX_CELLS);
+    if (n == 0) {
+        lat->flx_n = 0;
+        return LBEM_OK;
+    }
+    if (!cells || !maxflux) return fail(LBEM_EINVAL, "null flux-monitor arrays");
+    std::vector<int32_t> fc(n);
+    for (int32_t k = 0; k < n; ++k) {
+        if (cells[k] < 0 || cells[k] >= int64_t(lat->N))
+            return fail(LBEM_EINVAL, "flux-monitor cell %lld out of range", (long long)cells[k]);
+        fc[k] = int32_t(cells[k]);
+    }
+    hipStream_t s = lat->stream;
+    lbem_status st = hip_check(hipMemcpyAsync(lat->ws + lat->L.flx_cell, fc.data(), fc.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (!st) st = hip_check(hipStreamSynchronize(s), "synchronise");
+    if (st) return st;
+    lat->flx_n = n;
+    lat->flx_t0 = n_begin;
+    lat->flx_t1 = n_end;
+    lat->flx_max = maxflux;
+    return LBEM_OK;
+}
+
 lbem_status lbem_set_detector(lbem_lattice *lat, int32_t z) {
     if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
     if (z >= lat->d.nz) return fail(LBEM_EINVAL, "detector z = %d outside the lattice", z);
@@ -829,6 +876,8 @@ lbem_status lbem_step(lbem_lattice *lat, int64_t nsteps) {
     return step_impl(lat, nsteps, nullptr);
 }
 
+static void launch_flux(const lbem_lattice *lat);
+
 lbem_status lbem::step_impl(lbem_lattice *lat, int64_t nsteps, float *frames) {
     const WsLayout &L = lat->L;
     StepArgs a = base_step_args(lat);
@@ -858,6 +907,7 @@ lbem_status lbem::step_impl(lbem_lattice *lat, int64_t nsteps, float *frames) {
         const bool en = lat->en_every > 0 && (t - lat->en_t0) % lat->en_every == 0;
         a.en_part = en ? en_part : nullptr;
         a.E_out = frames ? frames + size_t(s) * 3 * lat->N : nullptr;
+        if (lat->flx_n > 0 && t >= lat->flx_t0 && t < lat->flx_t1) launch_flux(lat);
         dispatch_step(lat, a, int(t & 1));
         if (en) {
             double *dst = lat->en_series + ((t - lat->en_t0) / lat->en_every) % lat->en_cap;
@@ -892,7 +942,7 @@ static void dispatch_obs_storage(const lbem_lattice *lat, const ObsArgs &a) {
     }
 }
 
-static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, float *H, double *en_part) {
+static ObsArgs obs_args(const lbem_lattice *lat) {
     const WsLayout &L = lat->L;
     ObsArgs a{};
     a.pop = lat->ws + L.pop;
@@ -913,12 +963,49 @@ static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, floa
         a.src_tp = reinterpret_cast<const double *>(lat->ws + L.src_tp);
         a.src_t = double(lat->t);
     }
+    if (shifted(lat->d.storage)) a.rec = read_rec(lat, lat->t);
+    return a;
+}
+
+template <class M, int ODD>
+static void launch_flux_st(const lbem_lattice *lat, const ObsArgs &a) {
+    const int32_t *cells = reinterpret_cast<const int32_t *>(lat->ws + lat->L.flx_cell);
+    const uint32_t n = uint32_t(lat->flx_n);
+    const dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
+    switch (lat->d.storage) {
+        case LBEM_F32: hipLaunchKernelGGL((flux_kernel<M, ODD, StF32>), g, b, 0, lat->stream, a, cells, n, lat->flx_max); break;
+        case LBEM_BF16: hipLaunchKernelGGL((flux_kernel<M, ODD, StBF16>), g, b, 0, lat->stream, a, cells, n, lat->flx_max); break;
+        case LBEM_F16: hipLaunchKernelGGL((flux_kernel<M, ODD, StF16>), g, b, 0, lat->stream, a, cells, n, lat->flx_max); break;
+        case LBEM_BF16_SHIFTED:
+            hipLaunchKernelGGL((flux_kernel<M, ODD, StBF16S>), g, b, 0, lat->stream, a, cells, n, lat->flx_max);
+            break;
+        default: hipLaunchKernelGGL((flux_kernel<M, ODD, StF16S>), g, b, 0, lat->stream, a, cells, n, lat->flx_max); break;
+    }
+}
+
+// Fold |E x H| of the current state into the monitor's maxima.
+static void launch_flux(const lbem_lattice *lat) {
+    const ObsArgs a = obs_args(lat);
+    const int odd = int(lat->t & 1);
+    if (lat->d.model == LBEM_MM) {
+        if (odd) launch_flux_st<MM, 1>(lat, a);
+        else launch_flux_st<MM, 0>(lat, a);
+    } else if (lat->d.model == LBEM_MM_DIFF) {
+        if (odd) launch_flux_st<MMD, 1>(lat, a);
+        else launch_flux_st<MMD, 0>(lat, a);
+    } else {
+        if (odd) launch_flux_st<HV, 1>(lat, a);
+        else launch_flux_st<HV, 0>(lat, a);
+    }
+}
+
+static lbem_status observe(lbem_lattice *lat, float *E, float *B, float *D, float *H, double *en_part) {
+    ObsArgs a = obs_args(lat);
     a.E = E;
     a.B = B;
     a.D = D;
     a.H = H;
     a.en_part = en_part;
-    if (shifted(lat->d.storage)) a.rec = read_rec(lat, lat->t);
     const int odd = int(lat->t & 1);
     if (lat->d.model == LBEM_MM) {
         if (odd) dispatch_obs_storage<MM, 1>(lat, a);

@@ -15,6 +15,8 @@ Workloads (all synthetic; the paper uses no dataset):
 * ``dipole``      3-D vacuum box with a soft point current J_z = sin(2 pi n / 40)
                   at the centre and a 16-cell quadratic sigma sponge on all
                   faces (Section IV-C, point-source form).
+* ``radiation``   the dipole with the Gaussian current of Section IV-C and the
+                  cells of a sphere where the radiation pattern is measured.
 * ``multilayer``  ragged batch of 1-D instances with random dielectric layers
                   (Section IV-D generalised to random stacks).
 * ``slab``        inverse-design lattice: smooth random eps_r and sigma in a
@@ -176,6 +178,52 @@ def dipole(model: str = "mm", n: int = 256, period: float = 40.0, sponge: int = 
         currents = gaussian_currents(shape, (cx, cy, cz), alpha, amplitude, period)
     probes = [cell_index(shape, cx + d, cy, cz) for d in (4, 8, 16) if cx + d < nx]
     return Workload("dipole", model, shape, sigma=sg, currents=currents, probes=probes, steps=steps)
+
+
+@dataclass
+class Radiation:
+    """A radiation-pattern run (Section IV-C): a Gaussian dipole workload and
+    the cells of a sphere of radius R about the dipole, sampled on four
+    half-planes of constant azimuth, where the largest energy flux over one
+    period is measured."""
+    workload: Workload
+    cells: np.ndarray         # [K] int64
+    theta: np.ndarray         # [K] polar angle from the dipole axis z, radians
+    phi: np.ndarray           # [K] azimuth, radians
+    radius: np.ndarray        # [K] distance of each cell from the dipole centre
+    window: Tuple[int, int]   # time levels [n_begin, n_end) of one period
+    period: float             # steps
+    wavelength: float         # cells
+
+
+def radiation(model: str = "mm", n: int = 256, alpha: float = 0.5, amplitude: float = 1e-4, n_theta: int = 37,
+              sponge: int = 16) -> Radiation:
+    """Section IV-C radiation-pattern set-up on an n^3 vacuum box: Gaussian
+    current J_z = J0 exp(-alpha r^2) sin(2 pi t / T) with T = 0.1768 n / c,
+    wavelength lambda = c T, sample radius R = lambda (n / (2 lambda) - 2),
+    flux maximum taken over the period R + lambda <= c t < R + 2 lambda; the
+    run ends there.  Sample cells: polar angles 0..pi in n_theta steps on the
+    half-planes phi = 0, pi/2, pi, 3 pi/2, rounded to the nearest cell."""
+    c = VACUUM_SPEED[model]
+    period = 0.1768 * n / c
+    lam = c * period
+    R = lam * (n / (2.0 * lam) - 2.0)
+    n_begin = int(round((R + lam) / c))
+    n_end = n_begin + int(round(period))
+    w = dipole(model, n=n, period=period, sponge=sponge, steps=n_end, amplitude=amplitude, source="gaussian",
+               alpha=alpha)
+    ctr = np.array([n // 2, n // 2, n // 2], dtype=np.float64)
+    cells, th, ph, rad = [], [], [], []
+    for phi in (0.0, 0.5 * math.pi, math.pi, 1.5 * math.pi):
+        for theta in np.linspace(0.0, math.pi, n_theta):
+            d = R * np.array([math.sin(theta) * math.cos(phi), math.sin(theta) * math.sin(phi), math.cos(theta)])
+            p = np.rint(ctr + d)
+            cells.append(cell_index(w.shape, int(p[0]), int(p[1]), int(p[2])))
+            th.append(theta)
+            ph.append(phi)
+            rad.append(float(np.linalg.norm(p - ctr)))
+    return Radiation(w, np.array(cells, dtype=np.int64), np.array(th), np.array(ph), np.array(rad),
+                     (n_begin, n_end), period, lam)
 
 
 @dataclass

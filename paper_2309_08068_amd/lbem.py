@@ -37,6 +37,7 @@ SIGNATURES = {
     "lbem_set_plane_source": (_I32, [_P, _I32, _P, _P, _D]),
     "lbem_add_point_current": (_I32, [_P, _I32, _I32, _I32, _P, _D, _D]),
     "lbem_set_probes": (_I32, [_P, _I32, _P, _I64, _P]),
+    "lbem_set_flux_monitor": (_I32, [_P, _I32, _P, _I64, _I64, _P]),
     "lbem_set_detector": (_I32, [_P, _I32]),
     "lbem_detector_read": (_I32, [_P, _P]),
     "lbem_set_energy_series": (_I32, [_P, _I32, _I64, _P]),
@@ -221,6 +222,16 @@ class Lattice:
                                        _ptr(series)))
         self._keep["probes"] = series
         return series
+
+    def set_flux_monitor(self, cells: Sequence[int], n_begin: int, n_end: int) -> torch.Tensor:
+        """Largest |E x H| in each cell over the steps that collide time levels
+        n_begin .. n_end - 1 (FP64, on the device, filled as steps run)."""
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+        out = torch.zeros(len(cells), dtype=torch.float64, device=self.device)
+        check(self.lib.lbem_set_flux_monitor(self.h, len(cells), cells.ctypes.data_as(C.c_void_p), int(n_begin),
+                                             int(n_end), _ptr(out)))
+        self._keep["flux"] = out
+        return out
 
     def set_detector(self, z: int):
         check(self.lib.lbem_set_detector(self.h, int(z)))

@@ -102,3 +102,53 @@ def test_interface_spectral_radius():
     r_hv = np.abs(np.linalg.eigvals(global_operator("hv", eps))).max()
     assert r_mm < 1 + 1e-7
     assert r_hv > 1 + 1e-3
+
+
+def test_mm_fields_depend_only_on_pair_differences():
+    """The MM scheme in difference form rests on this: the E, B, D and H the MM
+    scheme produces depend on its populations only through the differences
+    f_{i0} - f_{i1} of each pair.  Adding the same arbitrary value to both
+    populations of every pair, and arbitrary values to the rest populations,
+    of a random state (random media, soft currents, a hard plane source) must
+    leave every field of the next steps unchanged.  Also: both populations of
+    a pair move along the same velocity, and the collision maps the pair
+    differences to themselves alone."""
+    shape = (5, 4, 6)
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(17)
+    eps, mu, sig = rng.uniform(1, 3, n), rng.uniform(1, 2, n), rng.uniform(0, 0.2, n)
+    currents = [(int(c), tuple(rng.normal(size=3)), 13.0, 0.4) for c in rng.choice(n, 3, replace=False)]
+    P = oracle.Problem("mm", shape, eps_r=eps, mu_r=mu, sigma=sig, currents=currents,
+                       plane=(2, (0.3, -0.2, 0.1), (0.05, 0.4, -0.1), 17.0))
+    f = rng.normal(size=(50, n))
+    g = f.copy()
+    pairs = [(r * 24 + p * 8 + i * 2, r * 24 + p * 8 + i * 2 + 1) for r in range(2) for p in range(3)
+             for i in range(4)]
+    for a, b in pairs:
+        s = rng.normal(size=n)
+        g[a] += s
+        g[b] += s
+    g[48:50] += rng.normal(size=(2, n))
+    V = oracle.velocities("mm")
+    assert all((V[a] == V[b]).all() for a, b in pairs)
+    for steps in (1, 7):
+        fa, ga = f.copy(), g.copy()
+        oracle.run(P, fa, 0, steps)
+        oracle.run(P, ga, 0, steps)
+        for x, y in zip(oracle.fields(P, fa, steps), oracle.fields(P, ga, steps)):
+            np.testing.assert_allclose(y, x, rtol=0, atol=1e-11 * np.abs(x).max())
+        # the streamed pair differences agree too
+        for a, b in pairs:
+            np.testing.assert_allclose(ga[a] - ga[b], fa[a] - fa[b], rtol=0, atol=1e-10)
+        # while changing one difference does change the fields
+        h = f.copy()
+        h[pairs[0][0], :] += 1.0
+        oracle.run(P, h, 0, steps)
+        assert np.abs(oracle.fields(P, h, steps)[0] - oracle.fields(P, fa, steps)[0]).max() > 1e-3
+    # collision: the image of a pure pair sum (f_{i0} = f_{i1}) has zero differences
+    C = collision_matrix("mm", 1.7, 1.3, 0.1)
+    for a, b in pairs:
+        u = np.zeros(50)
+        u[a] = u[b] = 1.0
+        out = C @ u
+        assert max(abs(out[x] - out[y]) for x, y in pairs) < 1e-14

@@ -174,6 +174,40 @@ def test_hertz_dipole_field(model):
         assert np.all((ratio > 0.6) & (ratio < 1.45))
 
 
+def max_flux(model, rad, series):
+    """Largest |E x H| (vacuum: H = B / mu0) over the measurement period, per sample cell."""
+    mu0 = EPS0_MU0[model][1]
+    E, H = series[..., :3], series[..., 3:] / mu0
+    S = np.linalg.norm(np.cross(E, H), axis=-1)
+    return S[rad.window[0]:rad.window[1]].max(axis=0)
+
+
+@pytest.mark.parametrize("model", ["mm", "hv"])
+def test_radiation_pattern(model):
+    """Section IV-C radiation pattern on a 96^3 box (8-cell sponge): the largest
+    energy flux over one period at R = lambda (L / (2 lambda) - 2), times r^2,
+    follows sin^2(theta) (normalised; on four azimuths), and its absolute value
+    is that of a Hertz dipole of moment p = sum(J) / omega, whose far-field flux
+    peaks at mu0 omega^4 p^2 sin^2(theta) / (16 pi^2 c) (twice Jackson's
+    time average).  Measured: pattern within 0.064 (MM) and 0.058 (HV) of
+    sin^2; equatorial absolute ratio 0.88-0.94 (MM) and 0.92-0.98 (HV), both
+    closing in under refinement (0.95-0.97 and 0.98-1.01 at 128^3)."""
+    rad = inputs.radiation(model, n=96, sponge=8)
+    w = rad.workload
+    P = oracle.Problem(model, w.shape, sigma=w.sigma, currents=w.currents)
+    f = oracle.init(P, *w.fields0())
+    out = oracle.run(P, f, 0, w.steps, probes=list(rad.cells))
+    smax = max_flux(model, rad, out["probes"]) * rad.radius ** 2
+    pattern = smax / smax.max()
+    assert np.abs(pattern - np.sin(rad.theta) ** 2).max() < 0.1
+    om = 2 * math.pi / rad.period
+    p = sum(c[1][2] for c in w.currents) / om
+    theory = EPS0_MU0[model][1] * om ** 4 * p ** 2 / (16 * math.pi ** 2 * C0[model])
+    eq = np.abs(rad.theta - math.pi / 2) < 0.3
+    ratio = smax[eq] / (theory * np.sin(rad.theta[eq]) ** 2)
+    assert np.all((ratio > 0.8) & (ratio < 1.1)), ratio
+
+
 def pulse_error(model, eps, scale):
     """1-D periodic pulse at speed 1/3, lattice and pulse width scaled together."""
     N, z0, w, travel = 600 * scale, 150.0 * scale, 20.0 * scale, 300 * scale
