@@ -311,8 +311,9 @@ lbem_status lbem_adjoint(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t k
  * All instances share the time level.  One call of lbem_batch_step advances
  * every instance by nsteps steps in ONE persistent kernel launch: each
  * workgroup owns whole instances (longest first, to the least-loaded
- * workgroup) and separates the steps of an instance by a workgroup barrier,
- * so no grid-wide synchronisation is needed.  In 1-D only the z components of
+ * workgroup) and separates the steps (or temporally blocked passes, see
+ * lbem_batch_set_blocking) of an instance by workgroup barriers, so no
+ * grid-wide synchronisation is needed.  In 1-D only the z components of
  * the velocities stream; MM's xy-plane populations and HV's +-x, +-y
  * populations stay in their cell.
  * ------------------------------------------------------------------------ */
@@ -338,10 +339,29 @@ lbem_status lbem_batch_set_fields(lbem_batch *b, const float *E, const float *B)
  * instance assignment. */
 lbem_status lbem_batch_set_launch(lbem_batch *b, int32_t threads, int32_t groups_per_cu);
 
-/* Time each candidate launch shape over trial_steps steps (the state is saved
- * and restored, so the batch is left unchanged) and keep the fastest.
- * Synchronises the stream.  The chosen shape is written to threads / groups_per_cu
- * (either may be NULL). */
+/* Temporal blocking of the persistent launch (0 = off, the default; else an
+ * even number in [2, 32]; needs 256 or 512 threads per workgroup).  Each pass
+ * over an instance advances it by steps_per_pass steps with its cells held in
+ * registers and the z-moving populations exchanged through LDS, so HBM sees
+ * one read and one write of the populations per pass instead of per step.
+ * An instance of at most `threads` cells stays resident for all the steps of
+ * a call; a longer one is swept in trapezoidal tiles of `threads` cells, each
+ * storing the threads - 2 steps_per_pass cells it updates exactly, with the
+ * overwritten halo cells kept in LDS.  The results are bit-identical to one
+ * step per pass: every post-collision value is rounded to the storage format
+ * between steps, as the stored form would be.  An odd first or last step of a
+ * call runs one step at a time.  Costs 2 steps_per_pass / (threads - 2
+ * steps_per_pass) extra collisions on long instances. */
+lbem_status lbem_batch_set_blocking(lbem_batch *b, int32_t steps_per_pass);
+lbem_status lbem_batch_get_blocking(lbem_batch *b, int32_t *steps_per_pass);
+
+/* Time each candidate launch shape over trial_steps steps (at least two
+ * passes for a temporally blocked candidate; the state is saved and restored,
+ * so the batch is left unchanged) and keep the fastest per step.  Candidates:
+ * one step per pass at 128 to 1024 threads, and temporal blocking at 256 or
+ * 512 threads with 8, 16 or 32 steps per pass.  Synchronises the stream.  The
+ * chosen shape is written to threads / groups_per_cu (either may be NULL);
+ * the chosen blocking is read with lbem_batch_get_blocking. */
 lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *threads, int32_t *groups_per_cu);
 
 /* Advance every instance by nsteps steps: one persistent kernel launch. */

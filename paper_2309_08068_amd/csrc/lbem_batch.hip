@@ -38,7 +38,10 @@ struct BatchArgs {
     size_t total;
     int64_t nsteps;
     int32_t parity;  // time level parity at the first step
+    int32_t tb_k;    // temporal blocking: steps per pass over an instance (even, <= kMaxBlockSteps)
 };
+
+constexpr int kMaxBlockSteps = 32;
 
 // One cell of a 1-D instance occupying global cells [s, s + L).  Populations
 // are in chunks of cells (PopLayout with rows of one cell): element (q, g) is
@@ -96,6 +99,156 @@ __global__ __launch_bounds__(T) void batch_persistent(BatchArgs a) {
                     cell_1d<M, 1, ST>(pop, a.pl, a.eps, a.mu, a.sig, s, L, i, nullptr);
             }
             lds_phase_barrier();  // the next step reads what neighbouring threads wrote
+        }
+    }
+}
+
+// ---------------------------------------------------------------- temporal blocking
+// Slot of population q among the populations of M with the same z velocity
+// (the LDS exchange arrays hold only the populations that move in 1-D).
+template <class M>
+__host__ __device__ constexpr int zslot(int q) {
+    int n = 0;
+    for (int p = 0; p < q; ++p)
+        if (M::vel(p, 2) == M::vel(q, 2)) ++n;
+    return n;
+}
+template <class M>
+__host__ __device__ constexpr int zcount(int sgn) {
+    int n = 0;
+    for (int q = 0; q < M::Q; ++q)
+        if (M::vel(q, 2) == sgn) ++n;
+    return n;
+}
+
+// One step of the cell a thread holds in registers: collision, the storage
+// format's rounding of every post-collision value (as the one-step schedule
+// stores and reloads them, so both schedules give the same bits), then
+// streaming through LDS: +z movers arrive from thread `left`, -z movers from
+// thread `right`.  xch is one of two alternating buffers, so one barrier per
+// step suffices: a thread can only overwrite a buffer after every thread has
+// passed the barrier that follows its reads of that buffer.
+template <class M, class ST, int T>
+__device__ __forceinline__ void tb_step(float (&f)[M::Q], const CellMedia &m, float *xch, uint32_t tid, uint32_t left,
+                                        uint32_t right) {
+    constexpr int NP = zcount<M>(1);
+    const float Js[3] = {0.f, 0.f, 0.f};
+    CellFields o;
+    Cell<M>::collide(f, m, Js, o);
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) {
+        f[q] = ST::cvt(ST::pack(f[q], 1.f), 1.f);
+        const int vz = M::vel(q, 2);
+        if (vz > 0) xch[zslot<M>(q) * T + tid] = f[q];
+        if (vz < 0) xch[(NP + zslot<M>(q)) * T + tid] = f[q];
+    }
+    lds_phase_barrier();
+#pragma unroll
+    for (int q = 0; q < M::Q; ++q) {
+        const int vz = M::vel(q, 2);
+        if (vz > 0) f[q] = xch[zslot<M>(q) * T + left];
+        if (vz < 0) f[q] = xch[(NP + zslot<M>(q)) * T + right];
+    }
+}
+
+// Temporally blocked form of batch_persistent.  Each pass advances an
+// instance by k steps (k even) with the cells held in registers:
+//   - L <= T: the whole instance is resident (thread i holds cell i, periodic
+//     neighbours) and one pass covers every even step of the call;
+//   - L > T: trapezoidal tiles of T cells, each computing the T - 2k cells
+//     it can update exactly (information moves one cell per step) and
+//     storing them in place; the halo cells a later tile needs at the old
+//     time level (the k cells left of its interior, overwritten by the tile
+//     before, and cells 0..k-1 where a right halo wraps past the end of the
+//     instance, overwritten by the first tile) are kept in LDS.
+// Between passes the state is at an even time level, where population q of
+// cell g sits in slot (q, g); an odd first or last step uses the one-step code.
+template <class M, class ST, int T>
+__global__ __launch_bounds__(T) void batch_tb(BatchArgs a) {
+    constexpr int Q = M::Q;
+    constexpr int NX = zcount<M>(1) + zcount<M>(-1);
+    __shared__ float xch[2][NX * T];
+    __shared__ float stash_left[kMaxBlockSteps * Q];
+    __shared__ float stash_right[kMaxBlockSteps * Q];
+    auto *pop = static_cast<typename ST::T *>(a.pop);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t k_max = uint32_t(max(2, min(a.tb_k, kMaxBlockSteps))) & ~1u;
+    const uint64_t C = a.pl.C;
+    const int i0 = a.wg_start[blockIdx.x], i1 = a.wg_start[blockIdx.x + 1];
+    for (int it = i0; it < i1; ++it) {
+        const int b = a.items[it];
+        const uint32_t s = uint32_t(a.inst_off[b]);
+        const uint32_t L = uint32_t(a.inst_off[b + 1]) - s;
+        int64_t rem = a.nsteps;
+        if (rem > 0 && (a.parity & 1)) {
+            for (uint32_t i = tid; i < L; i += T) cell_1d<M, 1, ST>(pop, a.pl, a.eps, a.mu, a.sig, s, L, i, nullptr);
+            lds_phase_barrier();
+            --rem;
+        }
+        uint32_t sw = 0;  // exchange buffer of the next step
+        while (rem >= 2) {
+            float f[Q];
+            if (L <= uint32_t(T)) {
+                const int64_t k = rem & ~int64_t(1);
+                const uint32_t c = tid < L ? tid : 0;
+                const uint64_t base = a.pl.base(s + c);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) f[q] = ST::cvt(pop[uint64_t(q) * C + base], 1.f);
+                const CellMedia m{a.eps[s + c], a.mu[s + c], a.sig[s + c]};
+                const uint32_t left = tid < L ? (tid == 0 ? L - 1 : tid - 1) : tid;
+                const uint32_t right = tid < L ? (tid + 1 == L ? 0 : tid + 1) : tid;
+                for (int64_t n = 0; n < k; ++n, sw ^= 1u) tb_step<M, ST, T>(f, m, xch[sw], tid, left, right);
+                if (tid < L) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) pop[uint64_t(q) * C + base] = ST::pack(f[q], 1.f);
+                }
+                lds_phase_barrier();
+                rem -= k;
+                continue;
+            }
+            const uint32_t k = uint32_t(rem < int64_t(k_max) ? rem & ~int64_t(1) : int64_t(k_max));
+            const uint32_t W = uint32_t(T) - 2 * k;  // cells a tile updates
+            const uint32_t ntile = (L + W - 1) / W;
+            for (uint32_t j = 0; j < ntile; ++j) {
+                const uint32_t start = j * W;
+                // cell of this thread: start - k + tid, wrapped into [0, L)
+                int64_t raw = int64_t(start) - k + tid;
+                const bool wrapped_right = raw >= int64_t(L);
+                const uint32_t c = uint32_t(raw < 0 ? raw + L : (wrapped_right ? raw - L : raw));
+                const uint64_t base = a.pl.base(s + c);
+                const bool from_left = j > 0 && tid < k;          // overwritten by tile j - 1
+                const bool from_right = wrapped_right && c < k;  // overwritten by tile 0
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    if (from_left) f[q] = stash_left[tid * Q + q];
+                    else if (from_right) f[q] = stash_right[c * Q + q];
+                    else f[q] = ST::cvt(pop[uint64_t(q) * C + base], 1.f);
+                }
+                lds_phase_barrier();  // stash reads done before the stash is rewritten
+                if (j + 1 < ntile && tid >= W && tid < W + k) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) stash_left[(tid - W) * Q + q] = f[q];
+                }
+                if (j == 0 && tid >= k && tid < 2 * k) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) stash_right[(tid - k) * Q + q] = f[q];
+                }
+                const CellMedia m{a.eps[s + c], a.mu[s + c], a.sig[s + c]};
+                const uint32_t left = tid == 0 ? 0 : tid - 1;  // edge threads read garbage that never
+                const uint32_t right = tid + 1 == uint32_t(T) ? tid : tid + 1;  // reaches the interior
+                for (uint32_t n = 0; n < k; ++n, sw ^= 1u) tb_step<M, ST, T>(f, m, xch[sw], tid, left, right);
+                const uint32_t w = min(W, L - start);
+                if (tid >= k && tid < k + w) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) pop[uint64_t(q) * C + base] = ST::pack(f[q], 1.f);
+                }
+                lds_phase_barrier();
+            }
+            rem -= k;
+        }
+        if (rem == 1) {
+            for (uint32_t i = tid; i < L; i += T) cell_1d<M, 0, ST>(pop, a.pl, a.eps, a.mu, a.sig, s, L, i, nullptr);
+            lds_phase_barrier();
         }
     }
 }
@@ -210,13 +363,14 @@ struct lbem_batch {
     PopLayout pl;
     int ncu;
     int threads, gpc, groups;
+    int tb_k;  // steps per temporally blocked pass, 0 = one step per pass
     int64_t t;
     // cached graph of one persistent launch
     hipGraphExec_t gexec;
     hipGraph_t graph;
     int64_t g_nsteps;
     int g_parity;
-    int g_threads, g_gpc;
+    int g_threads, g_gpc, g_tb;
 };
 
 namespace {
@@ -239,6 +393,7 @@ BatchArgs args_of(lbem_batch *b, int64_t nsteps) {
     a.total = b->total;
     a.nsteps = nsteps;
     a.parity = int32_t(b->t & 1);
+    a.tb_k = b->tb_k;
     return a;
 }
 
@@ -279,6 +434,11 @@ lbem_status plan(lbem_batch *b) {
 
 template <class M, class ST>
 void launch_persistent_t(lbem_batch *b, const BatchArgs &a, hipStream_t s) {
+    if (b->tb_k > 0) {
+        if (b->threads == 256) hipLaunchKernelGGL((batch_tb<M, ST, 256>), dim3(b->groups), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((batch_tb<M, ST, 512>), dim3(b->groups), dim3(512), 0, s, a);
+        return;
+    }
     switch (b->threads) {
         case 128: hipLaunchKernelGGL((batch_persistent<M, ST, 128>), dim3(b->groups), dim3(128), 0, s, a); break;
         case 256: hipLaunchKernelGGL((batch_persistent<M, ST, 256>), dim3(b->groups), dim3(256), 0, s, a); break;
@@ -445,12 +605,31 @@ lbem_status lbem_batch_set_launch(lbem_batch *b, int32_t threads, int32_t groups
     if (!b) return fail(LBEM_EINVAL, "batch is NULL");
     if (threads != 128 && threads != 256 && threads != 512 && threads != 1024)
         return fail(LBEM_EINVAL, "threads must be 128, 256, 512 or 1024");
+    if (b->tb_k > 0 && threads != 256 && threads != 512)
+        return fail(LBEM_EINVAL, "temporal blocking runs 256 or 512 threads per workgroup");
     if (groups_per_cu < 1 || int64_t(groups_per_cu) * b->ncu > kMaxGroups)
         return fail(LBEM_EINVAL, "groups_per_cu must be in [1, %d]", kMaxGroups / b->ncu);
     b->threads = threads;
     b->gpc = groups_per_cu;
     b->groups = b->ncu * groups_per_cu;
     return plan(b);
+}
+
+lbem_status lbem_batch_set_blocking(lbem_batch *b, int32_t steps_per_pass) {
+    if (!b) return fail(LBEM_EINVAL, "batch is NULL");
+    if (steps_per_pass != 0 &&
+        (steps_per_pass < 2 || steps_per_pass > kMaxBlockSteps || (steps_per_pass & 1)))
+        return fail(LBEM_EINVAL, "steps_per_pass must be 0 or even in [2, %d]", kMaxBlockSteps);
+    if (steps_per_pass > 0 && b->threads != 256 && b->threads != 512)
+        return fail(LBEM_EINVAL, "temporal blocking runs 256 or 512 threads per workgroup (see lbem_batch_set_launch)");
+    b->tb_k = steps_per_pass;
+    return LBEM_OK;
+}
+
+lbem_status lbem_batch_get_blocking(lbem_batch *b, int32_t *steps_per_pass) {
+    if (!b || !steps_per_pass) return fail(LBEM_EINVAL, "null argument");
+    *steps_per_pass = b->tb_k;
+    return LBEM_OK;
 }
 
 lbem_status lbem_batch_step(lbem_batch *b, int64_t nsteps) {
@@ -469,7 +648,7 @@ lbem_status lbem_batch_step_graph(lbem_batch *b, int64_t nsteps) {
     if (nsteps == 0) return LBEM_OK;
     const int parity = int(b->t & 1);
     if (!b->gexec || b->g_nsteps != nsteps || b->g_parity != parity || b->g_threads != b->threads ||
-        b->g_gpc != b->gpc) {
+        b->g_gpc != b->gpc || b->g_tb != b->tb_k) {
         drop_graph(b);
         // capture on a private stream (the null stream cannot be captured)
         hipStream_t cs = nullptr;
@@ -494,6 +673,7 @@ lbem_status lbem_batch_step_graph(lbem_batch *b, int64_t nsteps) {
         b->g_parity = parity;
         b->g_threads = b->threads;
         b->g_gpc = b->gpc;
+        b->g_tb = b->tb_k;
     }
     lbem_status st = hip_check(hipGraphLaunch(b->gexec, b->stream), "graph launch");
     if (!st) b->t += nsteps;
@@ -552,7 +732,10 @@ lbem_status lbem_batch_get_time(lbem_batch *b, int64_t *t) {
 lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *threads, int32_t *groups_per_cu) {
     if (!b) return fail(LBEM_EINVAL, "batch is NULL");
     if (trial_steps < 1) return fail(LBEM_EINVAL, "trial_steps must be >= 1");
-    static const int32_t cand[][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}, {1024, 1}, {128, 4}, {128, 8}};
+    // (threads, groups per CU, steps per temporally blocked pass)
+    static const int32_t cand[][3] = {{256, 1, 0},  {256, 2, 0},  {256, 4, 0},  {512, 1, 0},  {512, 2, 0},
+                                      {1024, 1, 0}, {128, 4, 0},  {128, 8, 0},  {256, 1, 8},  {256, 1, 16},
+                                      {256, 2, 8},  {256, 2, 16}, {512, 1, 8},  {512, 1, 16}, {512, 1, 32}};
     const size_t pb = b->L.backup - b->L.pop;
     const int64_t t_saved = b->t;
     lbem_status st = hip_check(hipMemcpyAsync(b->ws + b->L.backup, b->ws + b->L.pop, pb, hipMemcpyDeviceToDevice, b->stream), "backup");
@@ -561,23 +744,29 @@ lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *thr
     st = hip_check(hipEventCreate(&e0), "event");
     if (!st) st = hip_check(hipEventCreate(&e1), "event");
     float best = 1e30f;
-    int32_t bt = b->threads, bg = b->gpc;
+    int32_t bt = b->threads, bg = b->gpc, bk = b->tb_k;
     for (const auto &c : cand) {
         if (st) break;
         if (int64_t(c[1]) * b->ncu > kMaxGroups) continue;
+        b->tb_k = 0;
         st = lbem_batch_set_launch(b, c[0], c[1]);
+        if (!st) st = lbem_batch_set_blocking(b, c[2]);
         if (st) break;
+        // a blocked candidate is timed over at least two full passes
+        const int64_t steps = std::max<int64_t>(trial_steps, 2 * c[2]);
         launch_persistent(b, 2, b->stream);  // warm-up
         st = hip_check(hipEventRecord(e0, b->stream), "record");
-        if (!st) launch_persistent(b, trial_steps, b->stream);
+        if (!st) launch_persistent(b, steps, b->stream);
         if (!st) st = hip_check(hipEventRecord(e1, b->stream), "record");
         if (!st) st = hip_check(hipEventSynchronize(e1), "sync");
         float ms = 0.f;
         if (!st) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        if (!st) ms /= float(steps);
         if (!st && ms < best) {
             best = ms;
             bt = c[0];
             bg = c[1];
+            bk = c[2];
         }
         // restore the state for the next candidate
         if (!st) st = hip_check(hipMemcpyAsync(b->ws + b->L.pop, b->ws + b->L.backup, pb, hipMemcpyDeviceToDevice, b->stream), "restore");
@@ -586,7 +775,9 @@ lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *thr
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (st) return st;
+    b->tb_k = 0;
     st = lbem_batch_set_launch(b, bt, bg);
+    if (!st) st = lbem_batch_set_blocking(b, bk);
     if (st) return st;
     if (threads) *threads = bt;
     if (groups_per_cu) *groups_per_cu = bg;

@@ -61,6 +61,8 @@ SIGNATURES = {
     "lbem_batch_destroy": (_I32, [_P]),
     "lbem_batch_set_fields": (_I32, [_P, _P, _P]),
     "lbem_batch_set_launch": (_I32, [_P, _I32, _I32]),
+    "lbem_batch_set_blocking": (_I32, [_P, _I32]),
+    "lbem_batch_get_blocking": (_I32, [_P, C.POINTER(_I32)]),
     "lbem_batch_autotune": (_I32, [_P, _I32, C.POINTER(_I32), C.POINTER(_I32)]),
     "lbem_batch_step": (_I32, [_P, _I64]),
     "lbem_batch_step_graph": (_I32, [_P, _I64]),
@@ -406,7 +408,18 @@ class Batch:
     def set_launch(self, threads: int, groups_per_cu: int):
         check(self.lib.lbem_batch_set_launch(self.h, int(threads), int(groups_per_cu)))
 
+    def set_blocking(self, steps_per_pass: int):
+        """Temporal blocking: steps per pass over each instance (0 = off)."""
+        check(self.lib.lbem_batch_set_blocking(self.h, int(steps_per_pass)))
+
+    def blocking(self) -> int:
+        k = C.c_int32()
+        check(self.lib.lbem_batch_get_blocking(self.h, C.byref(k)))
+        return k.value
+
     def autotune(self, trial_steps: int = 20):
+        """Pick the fastest launch shape and blocking (state left unchanged);
+        returns (threads, groups per CU); the blocking is read with blocking()."""
         t, g = C.c_int32(), C.c_int32()
         check(self.lib.lbem_batch_autotune(self.h, int(trial_steps), C.byref(t), C.byref(g)))
         return t.value, g.value

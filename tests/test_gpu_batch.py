@@ -124,3 +124,78 @@ def test_batch_rejects_bad_offsets_and_media():
     with pytest.raises(lbem.LbemError) as e:
         lbem.Batch("mm", [0, 4], eps_r=np.full(4, 0.5))
     assert e.value.status == -4
+
+
+TB_LENGTHS = [1, 2, 3, 17, 255, 256, 257, 300, 511, 512, 513, 700, 1031, 2000, 5003]
+
+
+@pytest.mark.parametrize("model", ["mm", "hv", "mmd"])
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_temporal_blocking_is_bit_identical(model, storage):
+    """Temporally blocked passes (resident instances up to one workgroup of
+    cells, trapezoidal tiles with LDS-kept halos beyond) give the bits of one
+    step per pass, for every tile width and pass length, with odd first and
+    last steps, a last tile narrower than the halo, and the graph path."""
+    d = random_batch(77, TB_LENGTHS)
+    calls = (5, 16, 3, 40, 1, 2)
+
+    def run(threads, gpc, k, graph=False):
+        b = lbem.Batch(model, d["off"], d["eps"], d["mu"], d["sig"], storage=storage)
+        b.set_launch(threads, gpc)
+        b.set_blocking(k)
+        assert b.blocking() == k
+        b.set_fields(d["E0"], d["B0"])
+        for n in calls:
+            (b.step_graph if graph else b.step)(n)
+        assert b.time == sum(calls)
+        E, B = b.fields()
+        torch.cuda.synchronize()
+        return E.clone(), B.clone()
+
+    ref = run(256, 2, 0)
+    assert torch.isfinite(ref[0]).all()
+    for threads, gpc, k, graph in ((256, 1, 2, False), (256, 2, 8, False), (256, 1, 16, False), (512, 1, 8, False),
+                                   (512, 1, 32, False), (512, 1, 16, True), (256, 2, 32, True)):
+        out = run(threads, gpc, k, graph)
+        print(f"{model} {storage} threads {threads} k {k} graph {graph}: identical "
+              f"{torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])}", flush=True)
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), (threads, gpc, k, graph)
+
+
+def test_temporal_blocking_matches_oracle_and_autotune():
+    """A blocked run against the oracle instance by instance, and the
+    autotuner (which also tries blocked passes) leaving the state unchanged."""
+    lengths = [40, 511, 1500, 3001]
+    d = random_batch(5, lengths)
+    b = lbem.Batch("mm", d["off"], d["eps"], d["mu"], d["sig"])
+    b.set_launch(512, 1)
+    b.set_blocking(16)
+    b.set_fields(d["E0"], d["B0"])
+    b.step(3)
+    E0 = b.fields()[0].clone()
+    threads, gpc = b.autotune(4)
+    k = b.blocking()
+    assert k in (0, 8, 16, 32) and (k == 0 or threads in (256, 512))
+    assert b.time == 3 and torch.equal(b.fields()[0], E0)
+    b.step(36)
+    E, B = (x.double().cpu().numpy() for x in b.fields())
+    for i in range(len(lengths)):
+        s, e = d["off"][i], d["off"][i + 1]
+        Eo, Bo = oracle_instance("mm", d["eps"][s:e], d["mu"][s:e], d["sig"][s:e], d["E0"][:, s:e],
+                                 d["B0"][:, s:e], 39)
+        assert rel(E[:, s:e], Eo) < TOL and rel(B[:, s:e], Bo) < TOL, i
+
+
+def test_temporal_blocking_rejects_bad_settings():
+    b = lbem.Batch("hv", [0, 10, 30])
+    for k in (1, 3, 34, -2):
+        with pytest.raises(lbem.LbemError):
+            b.set_blocking(k)
+    b.set_launch(1024, 1)
+    with pytest.raises(lbem.LbemError):
+        b.set_blocking(8)
+    b.set_launch(512, 1)
+    b.set_blocking(8)
+    with pytest.raises(lbem.LbemError):
+        b.set_launch(128, 4)
+    assert b.blocking() == 8
