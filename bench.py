@@ -328,6 +328,17 @@ def main():
         variants = [v for v in variants if f"{v[0]}_{v[1]}" in keep]
     if args.profile:
         from paper_2309_08068_amd import inputs, lbem
+        if "batch" in args.only.split(","):
+            bt = inputs.multilayer("mm", steps=args.steps)
+            b = lbem.batch_from_inputs(bt)
+            threads, gpc = b.autotune(10)
+            b.step(64)
+            torch.cuda.synchronize()
+            print(f"# batch: launch {threads} x {gpc}, {b.blocking()} steps per pass; timed region = the last "
+                  f"launch ({args.steps} steps)", file=sys.stderr, flush=True)
+            b.step(args.steps)
+            torch.cuda.synchronize()
+            print(f"# profiled {args.steps} steps of the multilayer batch", file=sys.stderr, flush=True)
         for model, storage in variants:
             w = inputs.dipole(workload_model(model), n=args.n, steps=args.steps)
             lat = lbem.lattice_from_workload(w, storage=storage, model=model)

@@ -340,7 +340,7 @@ lbem_status lbem_batch_set_fields(lbem_batch *b, const float *E, const float *B)
 lbem_status lbem_batch_set_launch(lbem_batch *b, int32_t threads, int32_t groups_per_cu);
 
 /* Temporal blocking of the persistent launch (0 = off, the default; else an
- * even number in [2, 32]; needs 256 or 512 threads per workgroup).  Each pass
+ * even number in [2, 64]; needs 256 or 512 threads per workgroup).  Each pass
  * over an instance advances it by steps_per_pass steps with its cells held in
  * registers and the z-moving populations exchanged through LDS, so HBM sees
  * one read and one write of the populations per pass instead of per step.
@@ -359,7 +359,7 @@ lbem_status lbem_batch_get_blocking(lbem_batch *b, int32_t *steps_per_pass);
  * passes for a temporally blocked candidate; the state is saved and restored,
  * so the batch is left unchanged) and keep the fastest per step.  Candidates:
  * one step per pass at 128 to 1024 threads, and temporal blocking at 256 or
- * 512 threads with 8, 16 or 32 steps per pass.  Synchronises the stream.  The
+ * 512 threads with 16 to 64 steps per pass.  Synchronises the stream.  The
  * chosen shape is written to threads / groups_per_cu (either may be NULL);
  * the chosen blocking is read with lbem_batch_get_blocking. */
 lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *threads, int32_t *groups_per_cu);

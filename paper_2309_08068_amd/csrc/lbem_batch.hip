@@ -41,7 +41,7 @@ struct BatchArgs {
     int32_t tb_k;    // temporal blocking: steps per pass over an instance (even, <= kMaxBlockSteps)
 };
 
-constexpr int kMaxBlockSteps = 32;
+constexpr int kMaxBlockSteps = 64;
 
 // One cell of a 1-D instance occupying global cells [s, s + L).  Populations
 // are in chunks of cells (PopLayout with rows of one cell): element (q, g) is
@@ -216,13 +216,19 @@ __global__ __launch_bounds__(T) void batch_tb(BatchArgs a) {
                 const bool wrapped_right = raw >= int64_t(L);
                 const uint32_t c = uint32_t(raw < 0 ? raw + L : (wrapped_right ? raw - L : raw));
                 const uint64_t base = a.pl.base(s + c);
-                const bool from_left = j > 0 && tid < k;          // overwritten by tile j - 1
-                const bool from_right = wrapped_right && c < k;  // overwritten by tile 0
+                // every load is issued unconditionally (all addresses are cells of the
+                // instance), so the Q loads are in flight together; the halo cells an
+                // earlier tile has overwritten then take their old values from LDS
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    if (from_left) f[q] = stash_left[tid * Q + q];
-                    else if (from_right) f[q] = stash_right[c * Q + q];
-                    else f[q] = ST::cvt(pop[uint64_t(q) * C + base], 1.f);
+                for (int q = 0; q < Q; ++q) f[q] = ST::cvt(pop[uint64_t(q) * C + base], 1.f);
+                const CellMedia m{a.eps[s + c], a.mu[s + c], a.sig[s + c]};
+                if (j > 0 && tid < k) {  // overwritten by tile j - 1
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) f[q] = stash_left[tid * Q + q];
+                }
+                if (wrapped_right && c < k) {  // overwritten by tile 0
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) f[q] = stash_right[c * Q + q];
                 }
                 lds_phase_barrier();  // stash reads done before the stash is rewritten
                 if (j + 1 < ntile && tid >= W && tid < W + k) {
@@ -233,7 +239,6 @@ __global__ __launch_bounds__(T) void batch_tb(BatchArgs a) {
 #pragma unroll
                     for (int q = 0; q < Q; ++q) stash_right[(tid - k) * Q + q] = f[q];
                 }
-                const CellMedia m{a.eps[s + c], a.mu[s + c], a.sig[s + c]};
                 const uint32_t left = tid == 0 ? 0 : tid - 1;  // edge threads read garbage that never
                 const uint32_t right = tid + 1 == uint32_t(T) ? tid : tid + 1;  // reaches the interior
                 for (uint32_t n = 0; n < k; ++n, sw ^= 1u) tb_step<M, ST, T>(f, m, xch[sw], tid, left, right);
@@ -734,8 +739,8 @@ lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *thr
     if (trial_steps < 1) return fail(LBEM_EINVAL, "trial_steps must be >= 1");
     // (threads, groups per CU, steps per temporally blocked pass)
     static const int32_t cand[][3] = {{256, 1, 0},  {256, 2, 0},  {256, 4, 0},  {512, 1, 0},  {512, 2, 0},
-                                      {1024, 1, 0}, {128, 4, 0},  {128, 8, 0},  {256, 1, 8},  {256, 1, 16},
-                                      {256, 2, 8},  {256, 2, 16}, {512, 1, 8},  {512, 1, 16}, {512, 1, 32}};
+                                      {1024, 1, 0}, {128, 4, 0},  {128, 8, 0},  {256, 1, 16}, {256, 2, 16},
+                                      {256, 2, 32}, {512, 1, 16}, {512, 1, 32}, {512, 1, 48}, {512, 1, 64}};
     const size_t pb = b->L.backup - b->L.pop;
     const int64_t t_saved = b->t;
     lbem_status st = hip_check(hipMemcpyAsync(b->ws + b->L.backup, b->ws + b->L.pop, pb, hipMemcpyDeviceToDevice, b->stream), "backup");
