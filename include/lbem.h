@@ -340,7 +340,7 @@ lbem_status lbem_batch_set_fields(lbem_batch *b, const float *E, const float *B)
 lbem_status lbem_batch_set_launch(lbem_batch *b, int32_t threads, int32_t groups_per_cu);
 
 /* Temporal blocking of the persistent launch (0 = off, the default; else an
- * even number in [2, 64]; needs 256 or 512 threads per workgroup).  Each pass
+ * even number in [2, 64]; needs 256, 512 or 1024 threads per workgroup).  Each
  * over an instance advances it by steps_per_pass steps with its cells held in
  * registers and the z-moving populations exchanged through LDS, so HBM sees
  * one read and one write of the populations per pass instead of per step.
@@ -351,7 +351,8 @@ lbem_status lbem_batch_set_launch(lbem_batch *b, int32_t threads, int32_t groups
  * step per pass: every post-collision value is rounded to the storage format
  * between steps, as the stored form would be.  An odd first or last step of a
  * call runs one step at a time.  Costs 2 steps_per_pass / (threads - 2
- * steps_per_pass) extra collisions on long instances. */
+ * steps_per_pass) extra collisions on long instances.  Needs a population
+ * array below 2 GiB (LBEM_EINVAL otherwise). */
 lbem_status lbem_batch_set_blocking(lbem_batch *b, int32_t steps_per_pass);
 lbem_status lbem_batch_get_blocking(lbem_batch *b, int32_t *steps_per_pass);
 
@@ -359,7 +360,7 @@ lbem_status lbem_batch_get_blocking(lbem_batch *b, int32_t *steps_per_pass);
  * passes for a temporally blocked candidate; the state is saved and restored,
  * so the batch is left unchanged) and keep the fastest per step.  Candidates:
  * one step per pass at 128 to 1024 threads, and temporal blocking at 256 or
- * 512 threads with 16 to 64 steps per pass.  Synchronises the stream.  The
+ * 1024 threads with 16 to 64 steps per pass.  Synchronises the stream.  The
  * chosen shape is written to threads / groups_per_cu (either may be NULL);
  * the chosen blocking is read with lbem_batch_get_blocking. */
 lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *threads, int32_t *groups_per_cu);

@@ -39,6 +39,7 @@ struct BatchArgs {
     int64_t nsteps;
     int32_t parity;  // time level parity at the first step
     int32_t tb_k;    // temporal blocking: steps per pass over an instance (even, <= kMaxBlockSteps)
+    uint32_t pop_bytes;  // size of the population array (temporal blocking needs < 2^31)
 };
 
 constexpr int kMaxBlockSteps = 64;
@@ -125,10 +126,12 @@ __host__ __device__ constexpr int zcount(int sgn) {
 // format's rounding of every post-collision value (as the one-step schedule
 // stores and reloads them, so both schedules give the same bits), then
 // streaming through LDS: +z movers arrive from thread `left`, -z movers from
-// thread `right`.  xch is one of two alternating buffers, so one barrier per
-// step suffices: a thread can only overwrite a buffer after every thread has
-// passed the barrier that follows its reads of that buffer.
-template <class M, class ST, int T>
+// thread `right`.  With NB = 2, xch is one of two alternating buffers and one
+// barrier per step suffices: a thread can only overwrite a buffer after every
+// thread has passed the barrier that follows its reads of that buffer.  With
+// NB = 1 (1024 threads, where two buffers do not fit in LDS) a second
+// barrier separates the reads from the next step's writes.
+template <class M, class ST, int T, int NB>
 __device__ __forceinline__ void tb_step(float (&f)[M::Q], const CellMedia &m, float *xch, uint32_t tid, uint32_t left,
                                         uint32_t right) {
     constexpr int NP = zcount<M>(1);
@@ -149,6 +152,29 @@ __device__ __forceinline__ void tb_step(float (&f)[M::Q], const CellMedia &m, fl
         if (vz > 0) f[q] = xch[zslot<M>(q) * T + left];
         if (vz < 0) f[q] = xch[(NP + zslot<M>(q)) * T + right];
     }
+    if constexpr (NB == 1) lds_phase_barrier();
+}
+
+// Population access of the temporally blocked kernel through a buffer
+// resource: a per-thread byte offset (the cell) plus a uniform byte offset (the
+// population plane) held in a scalar register, so Q loads in flight cost no
+// address registers.  The hardware checks every offset against the array size.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(void *pop, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(pop, 0, int(bytes), 0x00020000);  // raw dwords, gfx9 word 3
+}
+template <class ST>
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(typename ST::T) == 4)
+        return ST::cvt(__builtin_bit_cast(typename ST::T, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0)), 1.f);
+    else
+        return ST::cvt(__builtin_bit_cast(typename ST::T, __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), int(soff), 0)), 1.f);
+}
+template <class ST>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    if constexpr (sizeof(typename ST::T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, ST::pack(v, 1.f)), r, int(voff), int(soff), 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, ST::pack(v, 1.f)), r, int(voff), int(soff), 0);
 }
 
 // Temporally blocked form of batch_persistent.  Each pass advances an
@@ -167,13 +193,16 @@ template <class M, class ST, int T>
 __global__ __launch_bounds__(T) void batch_tb(BatchArgs a) {
     constexpr int Q = M::Q;
     constexpr int NX = zcount<M>(1) + zcount<M>(-1);
-    __shared__ float xch[2][NX * T];
+    constexpr int NB = T >= 1024 ? 1 : 2;
+    __shared__ float xch[NB][NX * T];
     __shared__ float stash_left[kMaxBlockSteps * Q];
     __shared__ float stash_right[kMaxBlockSteps * Q];
     auto *pop = static_cast<typename ST::T *>(a.pop);
     const uint32_t tid = threadIdx.x;
     const uint32_t k_max = uint32_t(max(2, min(a.tb_k, kMaxBlockSteps))) & ~1u;
-    const uint64_t C = a.pl.C;
+    constexpr uint32_t S = sizeof(typename ST::T);
+    const uint32_t plane = a.pl.C * S;  // bytes between population planes of a chunk
+    const __amdgpu_buffer_rsrc_t rsrc = pop_rsrc(a.pop, a.pop_bytes);
     const int i0 = a.wg_start[blockIdx.x], i1 = a.wg_start[blockIdx.x + 1];
     for (int it = i0; it < i1; ++it) {
         const int b = a.items[it];
@@ -191,16 +220,16 @@ __global__ __launch_bounds__(T) void batch_tb(BatchArgs a) {
             if (L <= uint32_t(T)) {
                 const int64_t k = rem & ~int64_t(1);
                 const uint32_t c = tid < L ? tid : 0;
-                const uint64_t base = a.pl.base(s + c);
+                const uint32_t off = uint32_t(a.pl.base(s + c)) * S;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) f[q] = ST::cvt(pop[uint64_t(q) * C + base], 1.f);
+                for (int q = 0; q < Q; ++q) f[q] = buf_ld<ST>(rsrc, off, q * plane);
                 const CellMedia m{a.eps[s + c], a.mu[s + c], a.sig[s + c]};
                 const uint32_t left = tid < L ? (tid == 0 ? L - 1 : tid - 1) : tid;
                 const uint32_t right = tid < L ? (tid + 1 == L ? 0 : tid + 1) : tid;
-                for (int64_t n = 0; n < k; ++n, sw ^= 1u) tb_step<M, ST, T>(f, m, xch[sw], tid, left, right);
+                for (int64_t n = 0; n < k; ++n, sw ^= NB - 1u) tb_step<M, ST, T, NB>(f, m, xch[sw], tid, left, right);
                 if (tid < L) {
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) pop[uint64_t(q) * C + base] = ST::pack(f[q], 1.f);
+                    for (int q = 0; q < Q; ++q) buf_st<ST>(rsrc, off, q * plane, f[q]);
                 }
                 lds_phase_barrier();
                 rem -= k;
@@ -215,12 +244,12 @@ __global__ __launch_bounds__(T) void batch_tb(BatchArgs a) {
                 int64_t raw = int64_t(start) - k + tid;
                 const bool wrapped_right = raw >= int64_t(L);
                 const uint32_t c = uint32_t(raw < 0 ? raw + L : (wrapped_right ? raw - L : raw));
-                const uint64_t base = a.pl.base(s + c);
+                const uint32_t off = uint32_t(a.pl.base(s + c)) * S;
                 // every load is issued unconditionally (all addresses are cells of the
                 // instance), so the Q loads are in flight together; the halo cells an
                 // earlier tile has overwritten then take their old values from LDS
 #pragma unroll
-                for (int q = 0; q < Q; ++q) f[q] = ST::cvt(pop[uint64_t(q) * C + base], 1.f);
+                for (int q = 0; q < Q; ++q) f[q] = buf_ld<ST>(rsrc, off, q * plane);
                 const CellMedia m{a.eps[s + c], a.mu[s + c], a.sig[s + c]};
                 if (j > 0 && tid < k) {  // overwritten by tile j - 1
 #pragma unroll
@@ -241,11 +270,11 @@ __global__ __launch_bounds__(T) void batch_tb(BatchArgs a) {
                 }
                 const uint32_t left = tid == 0 ? 0 : tid - 1;  // edge threads read garbage that never
                 const uint32_t right = tid + 1 == uint32_t(T) ? tid : tid + 1;  // reaches the interior
-                for (uint32_t n = 0; n < k; ++n, sw ^= 1u) tb_step<M, ST, T>(f, m, xch[sw], tid, left, right);
+                for (uint32_t n = 0; n < k; ++n, sw ^= NB - 1u) tb_step<M, ST, T, NB>(f, m, xch[sw], tid, left, right);
                 const uint32_t w = min(W, L - start);
                 if (tid >= k && tid < k + w) {
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) pop[uint64_t(q) * C + base] = ST::pack(f[q], 1.f);
+                    for (int q = 0; q < Q; ++q) buf_st<ST>(rsrc, off, q * plane, f[q]);
                 }
                 lds_phase_barrier();
             }
@@ -399,6 +428,7 @@ BatchArgs args_of(lbem_batch *b, int64_t nsteps) {
     a.nsteps = nsteps;
     a.parity = int32_t(b->t & 1);
     a.tb_k = b->tb_k;
+    a.pop_bytes = uint32_t(std::min<size_t>(b->L.backup - b->L.pop, 0xffffffffu));
     return a;
 }
 
@@ -441,7 +471,8 @@ template <class M, class ST>
 void launch_persistent_t(lbem_batch *b, const BatchArgs &a, hipStream_t s) {
     if (b->tb_k > 0) {
         if (b->threads == 256) hipLaunchKernelGGL((batch_tb<M, ST, 256>), dim3(b->groups), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((batch_tb<M, ST, 512>), dim3(b->groups), dim3(512), 0, s, a);
+        else if (b->threads == 512) hipLaunchKernelGGL((batch_tb<M, ST, 512>), dim3(b->groups), dim3(512), 0, s, a);
+        else hipLaunchKernelGGL((batch_tb<M, ST, 1024>), dim3(b->groups), dim3(1024), 0, s, a);
         return;
     }
     switch (b->threads) {
@@ -610,8 +641,8 @@ lbem_status lbem_batch_set_launch(lbem_batch *b, int32_t threads, int32_t groups
     if (!b) return fail(LBEM_EINVAL, "batch is NULL");
     if (threads != 128 && threads != 256 && threads != 512 && threads != 1024)
         return fail(LBEM_EINVAL, "threads must be 128, 256, 512 or 1024");
-    if (b->tb_k > 0 && threads != 256 && threads != 512)
-        return fail(LBEM_EINVAL, "temporal blocking runs 256 or 512 threads per workgroup");
+    if (b->tb_k > 0 && threads < 256)
+        return fail(LBEM_EINVAL, "temporal blocking runs 256, 512 or 1024 threads per workgroup");
     if (groups_per_cu < 1 || int64_t(groups_per_cu) * b->ncu > kMaxGroups)
         return fail(LBEM_EINVAL, "groups_per_cu must be in [1, %d]", kMaxGroups / b->ncu);
     b->threads = threads;
@@ -625,8 +656,11 @@ lbem_status lbem_batch_set_blocking(lbem_batch *b, int32_t steps_per_pass) {
     if (steps_per_pass != 0 &&
         (steps_per_pass < 2 || steps_per_pass > kMaxBlockSteps || (steps_per_pass & 1)))
         return fail(LBEM_EINVAL, "steps_per_pass must be 0 or even in [2, %d]", kMaxBlockSteps);
-    if (steps_per_pass > 0 && b->threads != 256 && b->threads != 512)
-        return fail(LBEM_EINVAL, "temporal blocking runs 256 or 512 threads per workgroup (see lbem_batch_set_launch)");
+    if (steps_per_pass > 0 && b->threads < 256)
+        return fail(LBEM_EINVAL, "temporal blocking runs 256, 512 or 1024 threads per workgroup (see lbem_batch_set_launch)");
+    if (steps_per_pass > 0 && b->L.backup - b->L.pop >= (size_t(1) << 31))
+        return fail(LBEM_EINVAL, "temporal blocking needs a population array below 2 GiB (this batch has %zu bytes)",
+                    b->L.backup - b->L.pop);
     b->tb_k = steps_per_pass;
     return LBEM_OK;
 }
@@ -739,8 +773,9 @@ lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *thr
     if (trial_steps < 1) return fail(LBEM_EINVAL, "trial_steps must be >= 1");
     // (threads, groups per CU, steps per temporally blocked pass)
     static const int32_t cand[][3] = {{256, 1, 0},  {256, 2, 0},  {256, 4, 0},  {512, 1, 0},  {512, 2, 0},
-                                      {1024, 1, 0}, {128, 4, 0},  {128, 8, 0},  {256, 1, 16}, {256, 2, 16},
-                                      {256, 2, 32}, {512, 1, 16}, {512, 1, 32}, {512, 1, 48}, {512, 1, 64}};
+                                      {1024, 1, 0}, {128, 4, 0},  {128, 8, 0},  {256, 2, 16}, {256, 2, 32},
+                                      {512, 1, 16}, {512, 1, 32}, {512, 1, 48}, {512, 2, 32}, {1024, 1, 32},
+                                      {1024, 1, 48}, {1024, 1, 64}};
     const size_t pb = b->L.backup - b->L.pop;
     const int64_t t_saved = b->t;
     lbem_status st = hip_check(hipMemcpyAsync(b->ws + b->L.backup, b->ws + b->L.pop, pb, hipMemcpyDeviceToDevice, b->stream), "backup");
@@ -753,6 +788,7 @@ lbem_status lbem_batch_autotune(lbem_batch *b, int32_t trial_steps, int32_t *thr
     for (const auto &c : cand) {
         if (st) break;
         if (int64_t(c[1]) * b->ncu > kMaxGroups) continue;
+        if (c[2] > 0 && b->L.backup - b->L.pop >= (size_t(1) << 31)) continue;
         b->tb_k = 0;
         st = lbem_batch_set_launch(b, c[0], c[1]);
         if (!st) st = lbem_batch_set_blocking(b, c[2]);

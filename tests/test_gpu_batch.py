@@ -156,7 +156,7 @@ def test_temporal_blocking_is_bit_identical(model, storage):
     assert torch.isfinite(ref[0]).all()
     for threads, gpc, k, graph in ((256, 1, 2, False), (256, 2, 8, False), (256, 1, 16, False), (512, 1, 8, False),
                                    (512, 1, 32, False), (512, 1, 64, False), (512, 1, 16, True), (256, 2, 32, True),
-                                   (256, 1, 64, False)):
+                                   (256, 1, 64, False), (1024, 1, 32, False), (1024, 1, 64, True)):
         out = run(threads, gpc, k, graph)
         print(f"{model} {storage} threads {threads} k {k} graph {graph}: identical "
               f"{torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])}", flush=True)
@@ -176,7 +176,7 @@ def test_temporal_blocking_matches_oracle_and_autotune():
     E0 = b.fields()[0].clone()
     threads, gpc = b.autotune(4)
     k = b.blocking()
-    assert k in (0, 16, 32, 48, 64) and (k == 0 or threads in (256, 512))
+    assert k in (0, 16, 32, 48, 64) and (k == 0 or threads in (256, 512, 1024))
     assert b.time == 3 and torch.equal(b.fields()[0], E0)
     b.step(36)
     E, B = (x.double().cpu().numpy() for x in b.fields())
@@ -192,7 +192,7 @@ def test_temporal_blocking_rejects_bad_settings():
     for k in (1, 3, 35, 66, -2):
         with pytest.raises(lbem.LbemError):
             b.set_blocking(k)
-    b.set_launch(1024, 1)
+    b.set_launch(128, 4)
     with pytest.raises(lbem.LbemError):
         b.set_blocking(8)
     b.set_launch(512, 1)
