@@ -11,7 +11,8 @@ equilibrium-shifted BF16 storage and the MM scheme in difference form (24
 populations per cell, same E and B) are timed the same way and reported under
 "variants".  Further sections: the batched ragged 1-D multilayer workload, the
 adjoint on the 128 x 128 x 256 inverse-design lattice, the radiation pattern of
-the Gaussian dipole at 256^3 (flux monitor), the 384^3 precision
+the Gaussian dipole at 256^3 (flux monitor), the refinement study of Section
+IV (error against GPU time and distribution-function memory), the 384^3 precision
 sweep, and the FP64 oracle on the host cores.
 
 Prints one JSON line.  `value` is lattice updates per second (MLUPS) with the
@@ -306,6 +307,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=1500)
     ap.add_argument("--no-sweep", action="store_true", help="skip the 384^3 precision sweep")
     ap.add_argument("--no-radiation", action="store_true", help="skip the 256^3 radiation-pattern runs")
+    ap.add_argument("--no-study", action="store_true", help="skip the refinement study of Section IV")
     ap.add_argument("--sweep-n", type=int, default=384)
     ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--profile", action="store_true",
@@ -416,6 +418,11 @@ def main():
         line["radiation_pattern"] = [radiation_pattern(m, args.n) for m in ("mm", "hv", "mmd")]
         for r in line["radiation_pattern"]:
             print(f"# radiation: {r}", file=sys.stderr, flush=True)
+    if not args.no_study:
+        from paper_2309_08068_amd import study
+        line["refinement_study"] = study.study()
+        for r in line["refinement_study"]:
+            print(f"# study: {r}", file=sys.stderr, flush=True)
     if not args.no_sweep:
         line["precision_sweep"] = [time_precision(m, args.sweep_n, args.sweep_steps) for m in ("mm", "hv")]
     if not args.no_cpu_baseline:

@@ -54,6 +54,7 @@ class Workload:
     probes: List[int] = field(default_factory=list)
     det_z: Optional[int] = None
     steps: int = 0
+    meta: dict = field(default_factory=dict)  # experiment geometry used by the analysis
 
     @property
     def n(self) -> int:
@@ -178,6 +179,90 @@ def dipole(model: str = "mm", n: int = 256, period: float = 40.0, sponge: int = 
         currents = gaussian_currents(shape, (cx, cy, cz), alpha, amplitude, period)
     probes = [cell_index(shape, cx + d, cy, cz) for d in (4, 8, 16) if cx + d < nx]
     return Workload("dipole", model, shape, sigma=sg, currents=currents, probes=probes, steps=steps)
+
+
+# ------------------------------------------------------------ refinement study
+# The four experiments of Section IV with the paper's geometry, scaled to a
+# lattice of L cells along z (the "refinement" is L).
+
+def paper_pulse(shape, z0: float, alpha: float, speed: float):
+    """E_x = exp(-(z - z0)^2 / (2 alpha^2)), B_y = E_x / speed (eq. Initialpulse)."""
+    return gaussian_pulse(shape, z0, math.sqrt(2.0) * alpha, speed)
+
+
+def study_interface(model: str, L: int) -> Workload:
+    """Section IV-A: alpha = 0.05 L / sqrt(2), z0 = L/2 - L/6, eps_r 1 -> 2.5 at
+    L/2; run until the pulse has travelled L/3 in vacuum time (reflected pulse
+    back at L/3, transmitted one L / (6 sqrt(2.5)) past the interface)."""
+    shape = (1, 1, L)
+    z = np.arange(L)
+    c = VACUUM_SPEED[model]
+    eps = z_profile(shape, np.where(z < L // 2, 1.0, 2.5))
+    E0, B0 = paper_pulse(shape, L / 2 - L / 6, 0.05 * L / math.sqrt(2.0), c)
+    return Workload("study_interface", model, shape, eps_r=eps, E0=E0, B0=B0,
+                    steps=int(round((L / 3) / c)), meta={"z_if": L // 2, "eps2": 2.5})
+
+
+def study_skin(model: str, L: int) -> Workload:
+    """Section IV-B: hard source E = sin(omega t) x, B = E / C y at z = 0,
+    T = 17.68e-3 L / C, conductor sigma = 0.1 eps / T (eps = eps0, vacuum
+    permittivity of the model) for L / 4 <= z < L.  The paper's far end is
+    open; here L / 4 more cells carry a sin^2 sponge (up to sigma = 0.5) that
+    absorbs the wave leaving the conductor and the source's backward wave
+    before the periodic wrap brings either back.  Runs until the front has
+    crossed the lattice and three more periods; the amplitude is taken over
+    the last period."""
+    S = L // 4
+    shape = (1, 1, L + S)
+    z = np.arange(L + S)
+    c = VACUUM_SPEED[model]
+    eps0 = VACUUM_CONSTANTS[model][0]
+    T = 17.68e-3 * L / c
+    sigma = 0.1 * eps0 / T
+    zc = L // 4
+    ramp = np.sin(np.pi * np.clip(z - L, 0, S) / S) ** 2
+    sg = z_profile(shape, np.where(z >= zc, sigma + (0.5 - sigma) * ramp, 0.0))
+    plane = (0, (1.0, 0.0, 0.0), (0.0, 1.0 / c, 0.0), T)
+    steps = int(round(L / c + 3 * T))
+    return Workload("study_skin", model, shape, sigma=sg, plane=plane, steps=steps,
+                    meta={"z_c": zc, "z_end": L, "period": T, "sigma": sigma})
+
+
+def study_dipole(model: str, n: int, sponge: int = 8) -> Workload:
+    """Section IV-C: Gaussian current J0 exp(-alpha r^2) sin(omega t) z,
+    alpha = 0.5, J0 = 1e-4, T = 0.1768 n / C, t_max = 70 T / 25; field
+    amplitudes over the last period on the +x axis from the centre, out to
+    where the wave has been established for a period."""
+    c = VACUUM_SPEED[model]
+    T = 0.1768 * n / c
+    w = dipole(model, n=n, period=T, sponge=sponge, steps=int(round(70 * T / 25)), amplitude=1e-4,
+               source="gaussian", alpha=0.5)
+    cx = n // 2
+    r_max = min(int(c * (w.steps - T)), cx - sponge - 1)
+    rs = list(range(3, r_max + 1))
+    w.name = "study_dipole"
+    w.probes = [cell_index(w.shape, cx + r, cx, cx) for r in rs]
+    w.meta = {"period": T, "radii": rs, "J0": 1e-4, "alpha": 0.5}
+    return w
+
+
+def study_layers(model: str, L: int) -> Workload:
+    """Section IV-D: eps_r = 1, 1.3, 2, 3 with interfaces at z0, z0 + d, z0 + 3d
+    (z0 = L / 2, d = L / 20); pulse at z0 - L / 30 with alpha = L / (100 sqrt 2).
+    Runs until the transmitted pulse is L / 10 past the last interface."""
+    shape = (1, 1, L)
+    z = np.arange(L)
+    c = VACUUM_SPEED[model]
+    z0, d = L // 2, L // 20
+    bounds = [z0, z0 + d, z0 + 3 * d]
+    epsz = np.where(z < bounds[0], 1.0, np.where(z < bounds[1], 1.3, np.where(z < bounds[2], 2.0, 3.0)))
+    alpha = L / (100.0 * math.sqrt(2.0))
+    zp = z0 - L / 30
+    E0, B0 = paper_pulse(shape, zp, alpha, c)
+    travel = (bounds[0] - zp) + d * math.sqrt(1.3) + 2 * d * math.sqrt(2.0) + (L / 10) * math.sqrt(3.0)
+    return Workload("study_layers", model, shape, eps_r=z_profile(shape, epsz), E0=E0, B0=B0,
+                    steps=int(round(travel / c)),
+                    meta={"bounds": bounds, "eps": [1.0, 1.3, 2.0, 3.0], "z_pulse": zp, "alpha": alpha})
 
 
 @dataclass
