@@ -529,8 +529,8 @@ void launch_fields_st(lbem_batch *b, const BatchArgs &a, float *E, float *B) {
 }
 
 void drop_graph(lbem_batch *b) {
-    if (b->gexec) hipGraphExecDestroy(b->gexec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
     b->graph = nullptr;
 }
@@ -703,7 +703,7 @@ lbem_status lbem_batch_step_graph(lbem_batch *b, int64_t nsteps) {
                 st = hip_check(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0), "instantiate graph");
             }
         }
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         if (st) {
             drop_graph(b);
             return st;
