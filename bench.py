@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9  # FP32 lane-instructions/s without packed FP32
+VALU_PER_LU_BATCH = 335.5  # profiled VALU lane-instructions per update of the blocked multilayer batch
 # every population read and written once, 12 B of media; the equilibrium-shifted
 # formats also write and read one 16-byte record per cell
 BYTES_PER_LU = {("mm", "f32"): 2 * 50 * 4 + 12, ("mm", "bf16"): 2 * 50 * 2 + 12,
@@ -162,7 +164,15 @@ def time_batch(steps: int):
             "one_step_per_pass_frac": round(bpl * total * steps / wall_1 / 1e9 / HBM_PEAK_GBS, 4),
             "per_instance_loop_s": round(wall_pi, 3), "per_instance_sample_steps": sample,
             "speedup_vs_per_instance": round(wall_pi / wall, 1),
-            "speedup_vs_one_step_per_pass": round(wall_1 / wall, 2)}
+            "speedup_vs_one_step_per_pass": round(wall_1 / wall, 2),
+            # blocked passes are bound by vector-ALU issue: rocprofv3 SQ_INSTS_VALU gives about 335
+            # lane-instructions per update of this workload (1024 threads, 48 steps per pass, halo
+            # recomputation included); the part issues 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz without
+            # packed FP32
+            "roofline_blocked": {"bound": "alu", "unit": "T lane-instr/s", "peak": VALU_LANE_PEAK / 1e12,
+                                 "valu_per_lu_profiled": VALU_PER_LU_BATCH,
+                                 "achieved": round(mlups * 1e6 * VALU_PER_LU_BATCH / 1e12, 1),
+                                 "frac": round(mlups * 1e6 * VALU_PER_LU_BATCH / VALU_LANE_PEAK, 4)}}
 
 
 def time_adjoint(model: str, steps: int, K: int, keep: int):
