@@ -376,7 +376,8 @@ __global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
     __shared__ float sh[(ODD && !DIRECT) ? n_xshift<R>() : 1][RB];
     const uint32_t row = blockIdx.x;
     const uint32_t z = row / a.ny;
-    const uint32_t c = row * RB + threadIdx.x;
+    const bool live = threadIdx.x < a.nx;  // rows shorter than RB leave the last threads idle
+    const uint32_t c = row * a.nx + (live ? threadIdx.x : 0u);
     const size_t N = a.N;
     RowIO<R, StF32, RB> io(a.lam, a.pl, a.ny, a.nz, row);
     float mu[M::Q];
@@ -393,8 +394,10 @@ __global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
     }
     float gE, gS;
     AdjCell<M>::step(mu, E, m, int32_t(z) == a.det_z, a.E0 != nullptr, E0c, gE, gS);
-    a.g_eps[c] += gE;
-    a.g_sig[c] += gS;
+    if (live) {
+        a.g_eps[c] += gE;
+        a.g_sig[c] += gS;
+    }
     if (LATE) io.late(mu[0]);
     if (DIRECT) io.template scatter_direct<ODD>(mu, 1.f);
     else io.template scatter<ODD>(mu, sh, 1.f);

@@ -335,7 +335,7 @@ struct BatchLayout {
 PopLayout batch_pop_layout(int model, int storage, size_t total) {
     const uint32_t Q = uint32_t(model_pops(model));
     const uint32_t cells = kChunkBytes / (storage == LBEM_F32 ? 4u : 2u);
-    PopLayout pl{1u, 31u, uint32_t(total), 0};
+    PopLayout pl{1u, 31u, uint32_t(total), 0, 1u};
     if (total > cells) {
         uint32_t sh = 0;
         while ((2u << sh) <= cells) ++sh;

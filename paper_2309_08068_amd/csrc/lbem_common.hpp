@@ -102,10 +102,11 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t 
 // which keeps address translation and DRAM pages local.  A lattice with a
 // single chunk (C = N) is the plain [Q][N] layout.
 struct PopLayout {
-    uint32_t nx, rshift, C;  // x extent, log2 of rows per chunk, cells per chunk
+    uint32_t nx, rshift, C;  // x extent, log2 of rows per chunk, cells per chunk (with row padding)
     uint64_t QC;             // elements per chunk
+    uint32_t pitch;          // cells from one row of a chunk to the next (>= nx)
     __host__ __device__ uint64_t base(uint32_t row) const {
-        return uint64_t(row >> rshift) * QC + uint64_t(row & ((1u << rshift) - 1u)) * nx;
+        return uint64_t(row >> rshift) * QC + uint64_t(row & ((1u << rshift) - 1u)) * pitch;
     }
     __host__ __device__ uint64_t index(int q, uint32_t cell) const {
         const uint32_t row = cell / nx;
@@ -247,7 +248,8 @@ __device__ __forceinline__ void lds_phase_barrier() {
 }
 
 // Gather / scatter of the in-place AA streaming for a block that owns one
-// whole x-row of RB cells (y, z uniform).  Every HBM access is the aligned
+// whole x-row of nx <= RB cells (y, z uniform; threads past the row idle).
+// Every HBM access is the aligned
 // row segment of one population plane, with the non-temporal hint; the +-1 x
 // shifts of the odd parity go through the LDS array sh[n_xshift][RB], which
 // keeps partial cache lines out of the memory traffic.  The direct variant
@@ -259,14 +261,16 @@ struct RowIO {
     using T = typename ST::T;
     const char *pop;
     PopLayout L;
-    uint32_t ny, x, xo;
+    uint32_t ny, x, xo, nx;
+    bool live;  // x < nx: the row block has RB >= nx threads, those past the row idle
     uint32_t yr[3], zr[3];
 
     // x: this thread's cell along the row (threadIdx.x unless a row is split
-    // over several workgroups)
+    // over several workgroups); the row length is L.nx <= RB
     __device__ RowIO(const void *p, const PopLayout &l, uint32_t ny_, uint32_t nz, uint32_t row,
                      uint32_t x_ = threadIdx.x)
-        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_), xo(x_ * uint32_t(sizeof(T))) {
+        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_), xo(x_ * uint32_t(sizeof(T))), nx(l.nx),
+          live(x_ < l.nx) {
         const uint32_t y = row % ny_, z = row / ny_;
         yr[0] = y == 0 ? ny_ - 1 : y - 1;
         yr[1] = y;
@@ -276,6 +280,10 @@ struct RowIO {
         zr[2] = z + 1 == nz ? 0 : z + 1;
     }
     __device__ uint32_t row_of(int dy, int dz) const { return yr[dy + 1] + ny * zr[dz + 1]; }
+    // x + dx (|dx| <= 1), periodic along the row
+    __device__ uint32_t xw(int dx) const {
+        return dx > 0 ? (x + 1 >= nx ? 0 : x + 1) : dx < 0 ? (x == 0 ? nx - 1 : x - 1) : x;
+    }
     // byte offset of (q, row + (dy, dz), x = 0)
     __device__ uint64_t row_base(int q, int dy, int dz) const {
         return (L.base(row_of(dy, dz)) + uint64_t(q) * L.C) * sizeof(T);
@@ -283,37 +291,43 @@ struct RowIO {
     __device__ T *at(int q, int dy, int dz) const {
         return reinterpret_cast<T *>(const_cast<char *>(pop) + row_base(q, dy, dz) + xo);
     }
-    // x + dx, periodic along the row
     __device__ T *at_x(int q, int dy, int dz, int dx) const {
-        return reinterpret_cast<T *>(const_cast<char *>(pop) + row_base(q, dy, dz) +
-                                     ((x + uint32_t(RB + dx)) % uint32_t(RB)) * uint32_t(sizeof(T)));
+        return reinterpret_cast<T *>(const_cast<char *>(pop) + row_base(q, dy, dz) + xw(dx) * uint32_t(sizeof(T)));
     }
     // store addresses formed after the collision (see late_addresses)
     __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo), "+v"(x) : "v"(after)); }
-    // cell index of x + (dx, dy, dz), |d| <= 1, periodic (for per-cell arrays)
-    __device__ uint32_t cell(int dx, int dy, int dz) const {
-        return row_of(dy, dz) * uint32_t(RB) + (x + uint32_t(RB + dx)) % uint32_t(RB);
-    }
+    // cell index of x + (dx, dy, dz), |d| <= 1, periodic (for per-cell arrays; live threads only)
+    __device__ uint32_t cell(int dx, int dy, int dz) const { return row_of(dy, dz) * nx + xw(dx); }
 
+    // Idle threads (x >= nx) load and store nothing and take f = 0, but pass
+    // every barrier.
     template <int ODD>
     __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale) const {
-        if (!ODD) {
 #pragma unroll
-            for (int q = 0; q < M::Q; ++q) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
+        for (int q = 0; q < M::Q; ++q) f[q] = 0.f;
+        if (!ODD) {
+            if (live) {
+#pragma unroll
+                for (int q = 0; q < M::Q; ++q) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
+            }
         } else {
             // f_q(x) = slot (opp q, x - v_q): aligned source row, x shift in LDS
-            int k = 0;
+            if (live) {
+                int k = 0;
 #pragma unroll
-            for (int q = 0; q < M::Q; ++q) {
-                const T v = raw<T, true>(at(M::opp(q), -M::vel(q, 1), -M::vel(q, 2)));
-                if (M::vel(q, 0) == 0) f[q] = ST::cvt(v, inv_scale);
-                else sh[k++][x] = v;
+                for (int q = 0; q < M::Q; ++q) {
+                    const T v = raw<T, true>(at(M::opp(q), -M::vel(q, 1), -M::vel(q, 2)));
+                    if (M::vel(q, 0) == 0) f[q] = ST::cvt(v, inv_scale);
+                    else sh[k++][x] = v;
+                }
             }
             lds_phase_barrier();
-            k = 0;
+            if (live) {
+                int k = 0;
 #pragma unroll
-            for (int q = 0; q < M::Q; ++q)
-                if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][(x + RB - M::vel(q, 0)) % RB], inv_scale);
+                for (int q = 0; q < M::Q; ++q)
+                    if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][xw(-M::vel(q, 0))], inv_scale);
+            }
             lds_phase_barrier();
         }
     }
@@ -321,26 +335,35 @@ struct RowIO {
     template <int ODD>
     __device__ void scatter(const float (&f)[M::Q], T (*sh)[RB], float scale) const {
         if (!ODD) {
+            if (live) {
 #pragma unroll
-            for (int q = 0; q < M::Q; ++q) put<T, true>(at(M::opp(q), 0, 0), ST::pack(f[q], scale));
+                for (int q = 0; q < M::Q; ++q) put<T, true>(at(M::opp(q), 0, 0), ST::pack(f[q], scale));
+            }
         } else {
             // f'_q(x) goes to slot (q, x + v_q): x shift in LDS, aligned stores
-            int k = 0;
+            if (live) {
+                int k = 0;
 #pragma unroll
-            for (int q = 0; q < M::Q; ++q) {
-                if (M::vel(q, 0) == 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
-                else sh[k++][(x + M::vel(q, 0) + RB) % RB] = ST::pack(f[q], scale);
+                for (int q = 0; q < M::Q; ++q) {
+                    if (M::vel(q, 0) == 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
+                    else sh[k++][xw(M::vel(q, 0))] = ST::pack(f[q], scale);
+                }
             }
             lds_phase_barrier();
-            k = 0;
+            if (live) {
+                int k = 0;
 #pragma unroll
-            for (int q = 0; q < M::Q; ++q)
-                if (M::vel(q, 0) != 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), sh[k++][x]);
+                for (int q = 0; q < M::Q; ++q)
+                    if (M::vel(q, 0) != 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), sh[k++][x]);
+            }
         }
     }
 
     template <int ODD>
     __device__ void gather_direct(float (&f)[M::Q], float inv_scale) const {
+#pragma unroll
+        for (int q = 0; q < M::Q; ++q) f[q] = 0.f;
+        if (!live) return;
 #pragma unroll
         for (int q = 0; q < M::Q; ++q) {
             if (!ODD) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
@@ -354,6 +377,7 @@ struct RowIO {
 
     template <int ODD>
     __device__ void scatter_direct(const float (&f)[M::Q], float scale) const {
+        if (!live) return;
 #pragma unroll
         for (int q = 0; q < M::Q; ++q) {
             if (!ODD) put<T, true>(at(M::opp(q), 0, 0), ST::pack(f[q], scale));

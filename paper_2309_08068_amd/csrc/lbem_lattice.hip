@@ -129,19 +129,22 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
     const uint32_t row = blk / SEG, seg = blk % SEG;  // row = y + ny z
     const uint32_t x = seg * TB + threadIdx.x;
     const uint32_t z = row / a.ny;
-    const uint32_t c = row * RB + x;
+    const bool live = x < a.nx;  // rows shorter than RB leave the last threads idle
+    const uint32_t c = row * a.nx + (live ? x : 0u);
     const size_t N = a.N;
     RowIO<M, ST, RB> io(a.pop, a.pl, a.ny, a.nz, row, x);
     float f[M::Q];
     if (DIRECT) io.template gather_direct<ODD>(f, a.inv_scale);
     else io.template gather<ODD>(f, sh, a.inv_scale);
-    if constexpr (ST::kShift)
-        unshift<M>(f, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]),
-                   [&](int dx, int dy, int dz) { return io.cell(dx, dy, dz); });
+    if constexpr (ST::kShift) {
+        if (live)
+            unshift<M>(f, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]),
+                       [&](int dx, int dy, int dz) { return io.cell(dx, dy, dz); });
+    }
 
     CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
     float Js[3] = {0.f, 0.f, 0.f};
-    if (a.src_blk) {
+    if (a.src_blk && live) {
         const int s0 = a.src_blk[row], s1 = a.src_blk[row + 1];
         for (int k = s0; k < s1; ++k)
             if (a.src_cell[k] == int32_t(c)) {
@@ -157,19 +160,22 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
     if (plane) Cell<M>::equilibrium(f, m, a.Eimp, a.Bimp);
     if constexpr (ST::kShift)
         shift_out<M>(f, plane ? a.Eimp : o.E, plane ? a.Bimp : o.B, m.eps_r, m.mu_r,
-                     static_cast<u32x4 *>(a.rec[ODD ? 1 : 0]), c, true);
+                     static_cast<u32x4 *>(a.rec[ODD ? 1 : 0]), c, live);
 
     if (LATE) io.late(f[0]);
     if (DIRECT) io.template scatter_direct<ODD>(f, a.scale);
     else io.template scatter<ODD>(f, sh, a.scale);
 
     // ---- observation of the state this step collided
-    if (a.E_out) {
+    if (!live) {
+        for (int k = 0; k < 3; ++k) o.E[k] = o.B[k] = o.D[k] = o.H[k] = 0.f;
+    }
+    if (a.E_out && live) {
         __builtin_nontemporal_store(o.E[0], a.E_out + c);
         __builtin_nontemporal_store(o.E[1], a.E_out + N + c);
         __builtin_nontemporal_store(o.E[2], a.E_out + 2 * N + c);
     }
-    if (a.prb_blk) {
+    if (a.prb_blk && live) {
         const int p0 = a.prb_blk[row], p1 = a.prb_blk[row + 1];
         for (int k = p0; k < p1; ++k)
             if (a.prb_cell[k] == int32_t(c)) {
@@ -365,7 +371,7 @@ namespace lbem {
 WsLayout layout(const lbem_desc *d) {
     WsLayout L;
     const size_t N = size_t(d->nx) * d->ny * d->nz;
-    const size_t bu = row_block(d) ? row_block(d) : kBlock;
+    const size_t bu = row_block(d) ? size_t(d->nx) : kBlock;  // cells per block unit: a row, or kBlock cells
     const size_t nblocks = (N + bu - 1) / bu;
     const size_t nobs = (N + kBlock - 1) / kBlock;
     const size_t nxy = size_t(d->nx) * d->ny;
@@ -437,7 +443,7 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     lat->Q = model_pops(desc->model);
     lat->sbytes = storage_bytes(desc->storage);
     lat->N = uint32_t(size_t(desc->nx) * desc->ny * desc->nz);
-    lat->bu = row_block(desc) ? row_block(desc) : uint32_t(kBlock);
+    lat->bu = row_block(desc) ? uint32_t(desc->nx) : uint32_t(kBlock);
     lat->nblocks = uint32_t((size_t(lat->N) + lat->bu - 1) / lat->bu);
     lat->nobs = grid_for(lat->N);
     lat->scale = (is_f16(desc->storage) && desc->storage_scale != 0.0) ? float(desc->storage_scale) : 1.0f;

@@ -60,7 +60,8 @@ def gpu_grad(shape, d, nsteps, det_z, K, model="mm", keep=1):
 @pytest.mark.parametrize("shape,nsteps,K,keep", [((6, 5, 16), 40, 7, 1), ((6, 5, 16), 41, 41, 1),
                                                  ((6, 5, 16), 40, 7, 3), ((6, 5, 16), 40, 7, 6),
                                                  ((128, 2, 12), 25, 4, 2), ((256, 1, 6), 17, 5, 1),
-                                                 ((128, 1, 520), 12, 5, 1)])
+                                                 ((128, 1, 520), 12, 5, 1), ((200, 2, 12), 15, 4, 1),
+                                                 ((300, 1, 100), 12, 5, 2)])
 def test_adjoint_matches_fp64_autodiff(model, shape, nsteps, K, keep):
     """Gradients w.r.t. eps_r and sigma of every cell, including the dependence
     of the equilibrium initial state on eps_r; uneven last segment, a single

@@ -87,12 +87,16 @@ def run_oracle(model, shape, p, steps, real="f64", probes=None, det_z=None, ener
 
 
 # generic form (odd sizes, ragged last block, axes of length 1) and the row form
-# (x extent 128, 256, 384 or 512: one block per x-row, LDS x-shifts), in one
-# layout chunk and -- the last four, with more x-rows than a chunk holds
-# (512, 256, 128 and 128 rows) -- across chunks with a partial last chunk
+# (x extent 65..512: one block of 128, 256, 384 or 512 threads per x-row, LDS
+# x-shifts), in one layout chunk and -- (128, 9, 60) .. (512, 3, 45), with
+# more x-rows than a chunk holds -- across chunks with a partial last chunk;
+# of the last five, (100, 7, 9) takes the generic form and the others have
+# rows shorter than their block (idle threads past nx, rows padded to 128
+# bytes), (200, 9, 41) also across chunks
 SHAPES = [(1, 1, 17), (7, 5, 9), (16, 16, 16), (33, 3, 5), (300, 1, 1), (1, 40, 1), (9, 1, 31),
           (128, 3, 5), (256, 2, 3), (384, 1, 2), (512, 2, 1),
-          (128, 9, 60), (256, 20, 13), (384, 10, 13), (512, 3, 45)]
+          (128, 9, 60), (256, 20, 13), (384, 10, 13), (512, 3, 45),
+          (100, 7, 9), (193, 3, 5), (200, 9, 41), (300, 4, 7), (450, 3, 13)]
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -177,7 +181,8 @@ def test_shifted_storage_beats_plain_on_smooth_fields(model, plain, shifted, sca
 
 @pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("shape,tuning", [((12, 10, 14), None), ((128, 6, 14), None), ((128, 9, 60), None),
-                                          ((384, 3, 14), ((3, 7), (0, 2))), ((256, 4, 14), ((2, 3), (2, 0)))])
+                                          ((384, 3, 14), ((3, 7), (0, 2))), ((256, 4, 14), ((2, 3), (2, 0))),
+                                          ((200, 9, 14), ((3, 5), (1, 2)))])
 def test_observations_parity(model, shape, tuning):
     """Probe series, energy series and detector-plane accumulation (FP64 on both
     sides), in the generic and the row form of the step kernel, including rows
@@ -504,12 +509,15 @@ def test_unstable_and_invalid_media_rejected():
         lat.set_plane_source(4, (1, 0, 0), (0, 1, 0), 10.0)
 
 
-@pytest.mark.parametrize("model,storage", [("mm", "f32"), ("mm", "bf16"), ("hv", "f32"), ("mm", "bf16_shifted"),
-                                           ("hv", "f16_shifted"), ("mmd", "f32"), ("mmd", "bf16_shifted")])
-def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage):
+@pytest.mark.parametrize("model,storage,shape", [("mm", "f32", (256, 20, 13)), ("mm", "bf16", (256, 20, 13)),
+                                                 ("hv", "f32", (256, 20, 13)), ("mm", "bf16_shifted", (256, 20, 13)),
+                                                 ("hv", "f16_shifted", (256, 20, 13)), ("mmd", "f32", (256, 20, 13)),
+                                                 ("mmd", "bf16_shifted", (256, 20, 13)), ("mm", "f32", (200, 20, 13)),
+                                                 ("hv", "bf16_shifted", (200, 20, 13))])
+def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage, shape):
     """Every (address form, blocks-per-CU cap) choice of the step kernel gives
-    the same bits; autotune leaves the state as it found it."""
-    shape = (256, 20, 13)  # two layout chunks
+    the same bits; autotune leaves the state as it found it (two layout
+    chunks; a 200-cell row in a 256-thread block)."""
     p = random_problem(model, shape, seed=21)
     ref = None
     for form in ((0, 0), (1, 1), (0, 1), (2, 2), (2, 1), (4, 5), (6, 4), (3, 3), (7, 1)):
