@@ -54,11 +54,14 @@ inline PopLayout pop_layout(const lbem_desc *d) {
     const uint32_t s = d->storage == LBEM_F32 ? 4u : 2u;
     const uint32_t cells = kChunkBytes / s;
     const uint64_t rows = uint64_t(d->ny) * d->nz;
-    // row-form rows start on 128-byte boundaries (the padding cells are never
-    // touched): a row that starts mid-line costs every one of its Q plane
-    // accesses an extra partial cache line
-    const uint32_t al = 128u / s;
-    const uint32_t pitch = row_block(d) ? (uint32_t(d->nx) + al - 1u) / al * al : uint32_t(d->nx);
+    // row-form rows are a power of two of cells apart (the padding cells are
+    // never touched).  Measured on MI355X: rows that start mid-line cost every
+    // one of their Q plane accesses an extra partial cache line, and rows of
+    // 1.5 KB (384 cells) ran at 71-75 % of the HBM peak against 79 % with a
+    // 2 KB pitch (and 32 KB plane chunks instead of 24 KB)
+    uint32_t pitch = uint32_t(d->nx);
+    if (row_block(d))
+        while (pitch & (pitch - 1u)) pitch += pitch & (~pitch + 1u);  // next power of two
     PopLayout L{uint32_t(d->nx), 31u, uint32_t(rows * pitch), 0, pitch};
     if (row_block(d)) {
         uint32_t sh = 0;
