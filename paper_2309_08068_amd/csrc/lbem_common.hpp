@@ -266,11 +266,14 @@ struct RowIO {
     uint32_t yr[3], zr[3];
 
     // x: this thread's cell along the row (threadIdx.x unless a row is split
-    // over several workgroups); the row length is L.nx <= RB
+    // over several workgroups); the row length is L.nx <= RB.  An idle thread
+    // (x >= nx) loads the row's last cell, which keeps every load outside a
+    // branch, and stores nothing; in LDS it only writes its own slot x >= nx,
+    // which no live thread reads.
     __device__ RowIO(const void *p, const PopLayout &l, uint32_t ny_, uint32_t nz, uint32_t row,
                      uint32_t x_ = threadIdx.x)
-        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_), xo(x_ * uint32_t(sizeof(T))), nx(l.nx),
-          live(x_ < l.nx) {
+        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_ < l.nx ? x_ : l.nx - 1u),
+          xo((x_ < l.nx ? x_ : l.nx - 1u) * uint32_t(sizeof(T))), nx(l.nx), live(x_ < l.nx) {
         const uint32_t y = row % ny_, z = row / ny_;
         yr[0] = y == 0 ? ny_ - 1 : y - 1;
         yr[1] = y;
@@ -284,6 +287,8 @@ struct RowIO {
     __device__ uint32_t xw(int dx) const {
         return dx > 0 ? (x + 1 >= nx ? 0 : x + 1) : dx < 0 ? (x == 0 ? nx - 1 : x - 1) : x;
     }
+    // LDS slot of x + dx for a live thread; an idle one keeps to its own slot
+    __device__ uint32_t slot(int dx, uint32_t tx) const { return live ? xw(dx) : tx; }
     // byte offset of (q, row + (dy, dz), x = 0)
     __device__ uint64_t row_base(int q, int dy, int dz) const {
         return (L.base(row_of(dy, dz)) + uint64_t(q) * L.C) * sizeof(T);
@@ -296,44 +301,36 @@ struct RowIO {
     }
     // store addresses formed after the collision (see late_addresses)
     __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo), "+v"(x) : "v"(after)); }
-    // cell index of x + (dx, dy, dz), |d| <= 1, periodic (for per-cell arrays; live threads only)
+    // cell index of x + (dx, dy, dz), |d| <= 1, periodic (for per-cell arrays)
     __device__ uint32_t cell(int dx, int dy, int dz) const { return row_of(dy, dz) * nx + xw(dx); }
 
-    // Idle threads (x >= nx) load and store nothing and take f = 0, but pass
-    // every barrier.
+    // tx: the thread's own position in the row block (its LDS slot when idle)
     template <int ODD>
-    __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale) const {
-#pragma unroll
-        for (int q = 0; q < M::Q; ++q) f[q] = 0.f;
+    __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale, uint32_t tx) const {
         if (!ODD) {
-            if (live) {
 #pragma unroll
-                for (int q = 0; q < M::Q; ++q) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
-            }
+            for (int q = 0; q < M::Q; ++q) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
         } else {
             // f_q(x) = slot (opp q, x - v_q): aligned source row, x shift in LDS
-            if (live) {
-                int k = 0;
+            const uint32_t own = live ? x : tx;
+            int k = 0;
 #pragma unroll
-                for (int q = 0; q < M::Q; ++q) {
-                    const T v = raw<T, true>(at(M::opp(q), -M::vel(q, 1), -M::vel(q, 2)));
-                    if (M::vel(q, 0) == 0) f[q] = ST::cvt(v, inv_scale);
-                    else sh[k++][x] = v;
-                }
+            for (int q = 0; q < M::Q; ++q) {
+                const T v = raw<T, true>(at(M::opp(q), -M::vel(q, 1), -M::vel(q, 2)));
+                if (M::vel(q, 0) == 0) f[q] = ST::cvt(v, inv_scale);
+                else sh[k++][own] = v;
             }
             lds_phase_barrier();
-            if (live) {
-                int k = 0;
+            k = 0;
 #pragma unroll
-                for (int q = 0; q < M::Q; ++q)
-                    if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][xw(-M::vel(q, 0))], inv_scale);
-            }
+            for (int q = 0; q < M::Q; ++q)
+                if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][slot(-M::vel(q, 0), tx)], inv_scale);
             lds_phase_barrier();
         }
     }
 
     template <int ODD>
-    __device__ void scatter(const float (&f)[M::Q], T (*sh)[RB], float scale) const {
+    __device__ void scatter(const float (&f)[M::Q], T (*sh)[RB], float scale, uint32_t tx) const {
         if (!ODD) {
             if (live) {
 #pragma unroll
@@ -341,17 +338,18 @@ struct RowIO {
             }
         } else {
             // f'_q(x) goes to slot (q, x + v_q): x shift in LDS, aligned stores
-            if (live) {
-                int k = 0;
+            int k = 0;
 #pragma unroll
-                for (int q = 0; q < M::Q; ++q) {
-                    if (M::vel(q, 0) == 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
-                    else sh[k++][xw(M::vel(q, 0))] = ST::pack(f[q], scale);
+            for (int q = 0; q < M::Q; ++q) {
+                if (M::vel(q, 0) == 0) {
+                    if (live) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
+                } else {
+                    sh[k++][slot(M::vel(q, 0), tx)] = ST::pack(f[q], scale);
                 }
             }
             lds_phase_barrier();
             if (live) {
-                int k = 0;
+                k = 0;
 #pragma unroll
                 for (int q = 0; q < M::Q; ++q)
                     if (M::vel(q, 0) != 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), sh[k++][x]);
@@ -361,9 +359,6 @@ struct RowIO {
 
     template <int ODD>
     __device__ void gather_direct(float (&f)[M::Q], float inv_scale) const {
-#pragma unroll
-        for (int q = 0; q < M::Q; ++q) f[q] = 0.f;
-        if (!live) return;
 #pragma unroll
         for (int q = 0; q < M::Q; ++q) {
             if (!ODD) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
