@@ -382,7 +382,7 @@ __global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
     RowIO<R, StF32, RB> io(a.lam, a.pl, a.ny, a.nz, row);
     float mu[M::Q];
     if (DIRECT) io.template gather_direct<ODD>(mu, 1.f);
-    else io.template gather<ODD>(mu, sh, 1.f, threadIdx.x);
+    else io.template gather<ODD>(mu, sh, 1.f);
     const float E[3] = {__builtin_nontemporal_load(a.E + c), __builtin_nontemporal_load(a.E + N + c),
                         __builtin_nontemporal_load(a.E + 2 * N + c)};
     const CellMedia m{a.eps[c], a.mu[c], a.sig[c]};
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(RB) void adjoint_row_kernel(AdjArgs a) {
     }
     if (LATE) io.late(mu[0]);
     if (DIRECT) io.template scatter_direct<ODD>(mu, 1.f);
-    else io.template scatter<ODD>(mu, sh, 1.f, threadIdx.x);
+    else io.template scatter<ODD>(mu, sh, 1.f);
 }
 
 // g64 += scale * g32 and g32 = 0 (end of a segment; FP64 across segments)

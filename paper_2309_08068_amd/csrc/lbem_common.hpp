@@ -268,8 +268,8 @@ struct RowIO {
     // x: this thread's cell along the row (threadIdx.x unless a row is split
     // over several workgroups); the row length is L.nx <= RB.  An idle thread
     // (x >= nx) loads the row's last cell, which keeps every load outside a
-    // branch, and stores nothing; in LDS it only writes its own slot x >= nx,
-    // which no live thread reads.
+    // branch, and stores nothing; in LDS it only writes slot RB - 1 >= nx,
+    // which no live thread reads (idle threads only exist when nx < RB).
     __device__ RowIO(const void *p, const PopLayout &l, uint32_t ny_, uint32_t nz, uint32_t row,
                      uint32_t x_ = threadIdx.x)
         : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_ < l.nx ? x_ : l.nx - 1u),
@@ -287,8 +287,8 @@ struct RowIO {
     __device__ uint32_t xw(int dx) const {
         return dx > 0 ? (x + 1 >= nx ? 0 : x + 1) : dx < 0 ? (x == 0 ? nx - 1 : x - 1) : x;
     }
-    // LDS slot of x + dx for a live thread; an idle one keeps to its own slot
-    __device__ uint32_t slot(int dx, uint32_t tx) const { return live ? xw(dx) : tx; }
+    // LDS slot of x + dx for a live thread; idle ones share slot RB - 1
+    __device__ uint32_t slot(int dx) const { return live ? xw(dx) : uint32_t(RB - 1); }
     // byte offset of (q, row + (dy, dz), x = 0)
     __device__ uint64_t row_base(int q, int dy, int dz) const {
         return (L.base(row_of(dy, dz)) + uint64_t(q) * L.C) * sizeof(T);
@@ -304,15 +304,14 @@ struct RowIO {
     // cell index of x + (dx, dy, dz), |d| <= 1, periodic (for per-cell arrays)
     __device__ uint32_t cell(int dx, int dy, int dz) const { return row_of(dy, dz) * nx + xw(dx); }
 
-    // tx: the thread's own position in the row block (its LDS slot when idle)
     template <int ODD>
-    __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale, uint32_t tx) const {
+    __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale) const {
         if (!ODD) {
 #pragma unroll
             for (int q = 0; q < M::Q; ++q) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
         } else {
             // f_q(x) = slot (opp q, x - v_q): aligned source row, x shift in LDS
-            const uint32_t own = live ? x : tx;
+            const uint32_t own = slot(0);
             int k = 0;
 #pragma unroll
             for (int q = 0; q < M::Q; ++q) {
@@ -324,13 +323,13 @@ struct RowIO {
             k = 0;
 #pragma unroll
             for (int q = 0; q < M::Q; ++q)
-                if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][slot(-M::vel(q, 0), tx)], inv_scale);
+                if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][slot(-M::vel(q, 0))], inv_scale);
             lds_phase_barrier();
         }
     }
 
     template <int ODD>
-    __device__ void scatter(const float (&f)[M::Q], T (*sh)[RB], float scale, uint32_t tx) const {
+    __device__ void scatter(const float (&f)[M::Q], T (*sh)[RB], float scale) const {
         if (!ODD) {
             if (live) {
 #pragma unroll
@@ -344,7 +343,7 @@ struct RowIO {
                 if (M::vel(q, 0) == 0) {
                     if (live) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
                 } else {
-                    sh[k++][slot(M::vel(q, 0), tx)] = ST::pack(f[q], scale);
+                    sh[k++][slot(M::vel(q, 0))] = ST::pack(f[q], scale);
                 }
             }
             lds_phase_barrier();

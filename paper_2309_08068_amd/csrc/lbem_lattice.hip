@@ -135,7 +135,7 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
     RowIO<M, ST, RB> io(a.pop, a.pl, a.ny, a.nz, row, x);
     float f[M::Q];
     if (DIRECT) io.template gather_direct<ODD>(f, a.inv_scale);
-    else io.template gather<ODD>(f, sh, a.inv_scale, x);
+    else io.template gather<ODD>(f, sh, a.inv_scale);
     if constexpr (ST::kShift) {
         if (live)
             unshift<M>(f, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]),
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
 
     if (LATE) io.late(f[0]);
     if (DIRECT) io.template scatter_direct<ODD>(f, a.scale);
-    else io.template scatter<ODD>(f, sh, a.scale, x);
+    else io.template scatter<ODD>(f, sh, a.scale);
 
     // ---- observation of the state this step collided
     if (!live) {
