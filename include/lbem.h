@@ -109,11 +109,12 @@ lbem_status lbem_workspace_size(const lbem_desc *desc, size_t *bytes);
 
 /* Bytes of one population state (what save_state writes): the populations,
  * and for the shifted formats also the record plane the next step reads.  The
- * state is an opaque byte image: populations are stored in chunks of x-rows
- * (lattices with nx = 128, 256, 384 or 512 and more rows than one chunk
- * holds, at most 32 KB per population plane per chunk, the last chunk padded),
- * otherwise as [Q][N]; a state is only meaningful to a lattice with the same
- * descriptor. */
+ * state is an opaque byte image.  Lattices whose rows take the row form of
+ * the step kernel (see lbem_set_tuning) store each population plane with rows
+ * a power of two of cells apart, in chunks of at most 32 KB per population
+ * plane when they have more rows than one chunk holds (the last chunk
+ * padded); other lattices store [Q][N].  A state is only meaningful to a
+ * lattice with the same descriptor. */
 lbem_status lbem_state_size(const lbem_desc *desc, size_t *bytes);
 
 /* Create a lattice.
@@ -216,8 +217,10 @@ lbem_status lbem_energy(lbem_lattice *lat, double *out);
 
 /* Launch tuning of the step kernel, per parity (index 0 even, 1 odd time
  * level).  form[p] = kernel + 4 * order:
- *   kernel, for lattices whose x extent is 128, 256, 384 or 512 (one
- *     workgroup per x-row): 0 and 1 are the row form, whose +-1 x shifts go
+ *   kernel, for lattices whose x extent nx is 128, 256, 384 or 512, or
+ *     fills at least 3/4 of the next of 256, 384, 512 (one workgroup of that
+ *     many threads per x-row, those past nx idle): 0 and 1 are the row
+ *     form, whose +-1 x shifts go
  *     through LDS so that every HBM access is an aligned row, with store
  *     addresses formed before (0) or after (1, fewer registers) the
  *     collision; 2 addresses every neighbour directly; 3 does the same with

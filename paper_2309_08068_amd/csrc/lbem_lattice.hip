@@ -111,9 +111,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     }
 }
 
-// Row form of the step for lattices with x extent RB: TB threads per block,
-// RB / TB blocks per x-row (y and z are uniform per block), see RowIO.  Same
-// arithmetic as step_kernel, bit for bit.
+// Row form of the step for lattices with x extent nx <= RB: TB threads per
+// block, RB / TB blocks per x-row (y and z are uniform per block; threads
+// past nx idle), see RowIO.  Same arithmetic as step_kernel, bit for bit.
 // LATE = 1 forms the store addresses after the collision (see late_addresses);
 // DIRECT = 1 addresses the x-shifted cells in HBM instead of through LDS (a
 // split row, TB < RB, needs it).  Which variant is faster depends on model,
