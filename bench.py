@@ -59,11 +59,18 @@ STEP_KERNEL_SOURCES = ("include/lbem.h", "paper_2309_08068_amd/csrc/lbem_common.
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step-kernel sources with comments and blank space removed
+    (a documentation edit leaves the measured kernels, and so the hash, alone)."""
+    import re
+
     h = hashlib.sha256()
     for fn in STEP_KERNEL_SOURCES:
-        with open(os.path.join(ROOT, fn), "rb") as f:
-            h.update(fn.encode())
-            h.update(f.read())
+        with open(os.path.join(ROOT, fn), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(fn.encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
