@@ -111,12 +111,14 @@ def test_one_call_adjoint_equals_two_passes(model):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("model", ["hv", "mm", "mmd"])
-def test_adjoint_launch_forms_are_bit_identical(model):
+@pytest.mark.parametrize("model,shape", [("hv", (128, 1, 520)), ("mm", (128, 1, 520)), ("mmd", (128, 1, 520)),
+                                         ("hv", (200, 1, 300)), ("mm", (300, 2, 40))])
+def test_adjoint_launch_forms_are_bit_identical(model, shape):
     """Every launch form of the adjoint kernel (LDS x-shifts with early or late
     store addresses, direct addressing), per parity, gives the same bits, twice
-    in a row, on a lattice of two layout chunks; the automatic choice too."""
-    shape, nsteps, K = (128, 1, 520), 12, 5
+    in a row, on a lattice of two layout chunks (also with rows shorter than
+    their block); the automatic choice too."""
+    nsteps, K = 12, 5
     d = smooth_case(shape, 5)
     ref = None
     for form in ((0, 0), (1, 1), (2, 2), (0, 2), (2, 0), (1, 0), None, (0, 0)):

@@ -130,7 +130,7 @@ TB_LENGTHS = [1, 2, 3, 17, 255, 256, 257, 300, 511, 512, 513, 700, 1031, 2000, 5
 
 
 @pytest.mark.parametrize("model", ["mm", "hv", "mmd"])
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
 def test_temporal_blocking_is_bit_identical(model, storage):
     """Temporally blocked passes (resident instances up to one workgroup of
     cells, trapezoidal tiles with LDS-kept halos beyond) give the bits of one
