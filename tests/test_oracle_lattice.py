@@ -152,3 +152,108 @@ def test_mm_fields_depend_only_on_pair_differences():
         u[a] = u[b] = 1.0
         out = C @ u
         assert max(abs(out[x] - out[y]) for x, y in pairs) < 1e-14
+
+
+def transverse_block(model, eps_z, kx, mu_z=None, sig_z=None):
+    """One step restricted to fields exp(i kx x) g(z) on a lattice whose media
+    vary along z only (so kx is conserved): g(z + v_z, q) <- exp(-i kx v_x)
+    [C(z) g(z)]_q, assembled from the single-cell collision and the velocity
+    table, independently of the lattice stepper."""
+    nz = len(eps_z)
+    Q = oracle.NQ[model]
+    V = oracle.velocities(model)
+    mu_z = np.ones(nz) if mu_z is None else np.asarray(mu_z, float)
+    sig_z = np.zeros(nz) if sig_z is None else np.asarray(sig_z, float)
+    phase = np.exp(-1j * kx * V[:, 0])
+    cache = {}
+    A = np.zeros((Q * nz, Q * nz), complex)  # row / column index q * nz + z
+    for z in range(nz):
+        key = (eps_z[z], mu_z[z], sig_z[z])
+        if key not in cache:
+            cache[key] = collision_matrix(model, *key)
+        C = cache[key]
+        for q in range(Q):
+            A[q * nz + (z + V[q, 2]) % nz, np.arange(Q) * nz + z] += phase[q] * C[q]
+    return A
+
+
+def lattice_block(model, nx, eps_z, m):
+    """The same restriction taken from the oracle's lattice stepper on an
+    nx x 1 x nz lattice: the step applied to cos(kx x) and sin(kx x) profiles,
+    kx = 2 pi m / nx, projected back onto them (a real block whose eigenvalues
+    are those of transverse_block at kx and -kx)."""
+    nz = len(eps_z)
+    Q = oracle.NQ[model]
+    P = oracle.Problem(model, (nx, 1, nz), eps_r=np.repeat(np.asarray(eps_z, float), nx))
+    x = np.arange(nx)
+    basis = [np.cos(2 * math.pi * m * x / nx), np.sin(2 * math.pi * m * x / nx)]
+    nb = 2 * Q * nz
+    A = np.zeros((nb, nb))
+    col = 0
+    for fa in basis:
+        for q in range(Q):
+            for z in range(nz):
+                f = np.zeros((Q, nz, nx))
+                f[q, z] = fa
+                f = f.reshape(Q, nz * nx)
+                oracle.run(P, f, 0, 1)
+                g = f.reshape(Q, nz, nx)
+                A[:, col] = np.concatenate([(g @ fb / (fb @ fb)).reshape(-1) for fb in basis])
+                col += 1
+    return A
+
+
+def radius(A):
+    return np.abs(np.linalg.eigvals(A)).max()
+
+
+OBLIQUE = np.linspace(0.05, math.pi - 0.05, 16)
+OBLIQUE_FINE = np.linspace(0.05, math.pi - 0.05, 48)
+
+
+def test_mm_growth_at_oblique_wavenumbers():
+    """Reading of Section II-A's stability claim on lattices of more than one
+    dimension: the MM global operator has eigenvalues off the unit circle
+    wherever eps_r or mu_r varies in space, for waves whose wavenumber across
+    the variation lies strictly between 0 and pi.
+
+    - 1-D lattices (kx = 0 only): radius 1 for stepped and smooth eps_r(z)
+      and mu_r(z).  This is why the 1-D interface and multilayer runs stay
+      bounded.
+    - Oblique waves (some kx in (0, pi)): radius > 1 for a step, a smooth
+      cosine profile, a 1 % contrast, a background slower than vacuum, a
+      mu_r step and an impedance-matched step (eps_r = mu_r) alike.
+    - kx = pi, sigma-only variation and homogeneous media: radius 1.
+    The modified HV model, bounded in 1-D on a smooth profile, grows for
+    oblique waves on it too.
+    The block assembled from the single-cell collision equals the one taken
+    from the lattice stepper (same spectral radius), so the growth is the
+    scheme's, not an artefact of the assembly."""
+    nz = 8
+    z = np.arange(nz)
+    step = np.where(z < nz // 2, 1.0, 2.0)
+    smooth = 1.5 - 0.5 * np.cos(2 * math.pi * z / nz)
+    # the lattice stepper agrees with the assembly (kx = 3 pi / 4 on 8 x 1 x 8)
+    r_lat = radius(lattice_block("mm", 8, step, 3))
+    r_asm = radius(transverse_block("mm", step, 3 * math.pi / 4))
+    assert abs(r_lat - r_asm) < 1e-6
+    assert r_asm > 1.02
+    stable = 1 + 1e-6  # vacuum sits on the stability limit: computed radii carry ~1e-8
+    for prof in (dict(eps_z=step), dict(eps_z=smooth), dict(eps_z=np.ones(nz), mu_z=step),
+                 dict(eps_z=step, mu_z=step)):
+        assert radius(transverse_block("mm", kx=0.0, **prof)) < stable
+        assert radius(transverse_block("mm", kx=math.pi, **prof)) < stable
+        assert max(radius(transverse_block("mm", kx=kx, **prof)) for kx in OBLIQUE) > 1 + 1e-3, prof
+    for eps_z in (np.where(z < nz // 2, 1.0, 1.01), np.where(z < nz // 2, 2.0, 4.0)):
+        # growth bands narrow with the contrast: a finer grid of kx finds them
+        assert max(radius(transverse_block("mm", eps_z, kx)) for kx in OBLIQUE_FINE) > 1 + 5e-4
+    for kx in np.linspace(0.0, math.pi, 9):
+        assert radius(transverse_block("mm", np.ones(nz), kx, sig_z=np.where(z < nz // 2, 0.0, 0.1))) < stable
+        assert radius(transverse_block("mm", np.full(nz, 2.0), kx)) < stable
+    # the modified HV model: bounded in 1-D on a smooth 16-cell profile (it
+    # grows at steps, see test_interface_spectral_radius), but not for oblique
+    # waves on the same profile
+    z16 = np.arange(16)
+    smooth16 = 1.5 - 0.5 * np.cos(2 * math.pi * z16 / 16)
+    assert radius(transverse_block("hv", smooth16, 0.0)) < stable
+    assert max(radius(transverse_block("hv", smooth16, kx)) for kx in OBLIQUE) > 1 + 1e-3

@@ -248,3 +248,38 @@ def test_energy_nearly_conserved(model):
     out = oracle.run(P, f, 0, 1000, energy_every=50)
     u = out["energy"]
     assert np.abs(u / u[0] - 1).max() < 2e-3
+
+
+@pytest.mark.parametrize("model", ["mm", "hv"])
+@pytest.mark.parametrize("er,mr", [(1.0, 1.0), (2.5, 1.0), (1.5, 2.0)])
+def test_travelling_pulse_equipartition(model, er, mr):
+    """The reported D and H (Section I-B: D = eps E, H = B / mu with eps =
+    eps_r eps0 and mu = mu_r mu0, in each model's lattice constants).  A pulse
+    released with an electric field only splits into two counter-propagating
+    pulses; in a travelling wave the electric and magnetic energies are equal,
+    so once the halves have separated sum E.D = sum B.H, each half of the
+    initial energy.  H = B / mu_r (no mu0, as Section II's H formula prints it)
+    or H = B / mu0 (no mu_r) would miss this by the factor mu0 or mu_r; the
+    test shows that it would."""
+    nz, z0, w = 1200, 600.0, 16.0
+    v = C0[model] / math.sqrt(er * mr)
+    E0, _ = inputs.gaussian_pulse((1, 1, nz), z0, w, v)
+    B0 = np.zeros_like(E0)
+    P = oracle.Problem(model, (1, 1, nz), eps_r=np.full(nz, er), mu_r=np.full(nz, mr))
+    f = oracle.init(P, E0, B0)
+    E, B, D, H = oracle.fields(P, f, 0)
+    u0 = 0.5 * (E * D).sum()
+    assert abs((B * H).sum()) < 1e-12 * u0
+    steps = int(250 / v)
+    oracle.run(P, f, 0, steps)
+    E, B, D, H = oracle.fields(P, f, steps)
+    ue, um = 0.5 * (E * D).sum(), 0.5 * (B * H).sum()
+    assert abs(ue / um - 1) < 1e-3, (ue, um)
+    assert abs((ue + um) / u0 - 1) < 2e-3
+    # the two halves are apart (no overlap left to trade energy)
+    ex = E[0]
+    assert np.abs(ex[int(z0) - 40:int(z0) + 40]).max() < 1e-3 * np.abs(ex).max()
+    eps0, mu0 = EPS0_MU0[model]
+    for wrong in (B / mr, B / mu0):
+        if not np.allclose(wrong, H):
+            assert abs(ue / (0.5 * (B * wrong).sum()) - 1) > 0.3
