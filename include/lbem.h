@@ -51,9 +51,9 @@ typedef enum {
     LBEM_EINVAL = -1,      /* bad argument (null, size, range, mismatched state) */
     LBEM_ENOMEM = -2,      /* workspace or buffer smaller than required */
     LBEM_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
-    LBEM_EUNSTABLE = -4,   /* media outside the stable range of the scheme */
+    LBEM_EUNSTABLE = -4,   /* media outside the stable range of the scheme; lbem_check: energy above the bound */
     LBEM_ESTATE = -5,      /* call not valid in the lattice's current state */
-    LBEM_ENOTFINITE = -6   /* non-finite media */
+    LBEM_ENOTFINITE = -6   /* non-finite media; lbem_check: non-finite energy or detector sum */
 } lbem_status;
 
 typedef enum { LBEM_MM = 0, LBEM_HV = 1, LBEM_MM_DIFF = 2 } lbem_model;
@@ -104,8 +104,15 @@ int32_t lbem_version(void);
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *lbem_last_error(void);
 
-/* Bytes of device workspace lbem_create needs for this descriptor. */
+/* Bytes of device workspace lbem_create needs for this descriptor.  The
+ * workspace holds the populations (the state; see lbem_state_size for their
+ * layout and padding), the record planes of the shifted formats, the media,
+ * FP64 partial sums and the source, probe and monitor tables. */
 lbem_status lbem_workspace_size(const lbem_desc *desc, size_t *bytes);
+
+/* The same size as a return value: 0 if the descriptor is invalid (the reason
+ * is in lbem_last_error). */
+size_t lbem_workspace_bytes(const lbem_desc *desc);
 
 /* Bytes of one population state (what save_state writes): the populations,
  * and for the shifted formats also the record plane the next step reads.  The
@@ -114,7 +121,13 @@ lbem_status lbem_workspace_size(const lbem_desc *desc, size_t *bytes);
  * a power of two of cells apart, in chunks of at most 32 KB per population
  * plane when they have more rows than one chunk holds (the last chunk
  * padded); other lattices store [Q][N].  A state is only meaningful to a
- * lattice with the same descriptor. */
+ * lattice with the same descriptor.
+ * The padding is never read or written by the step kernels, so it costs no
+ * traffic there, but it is real device memory: rows of nx cells take
+ * 128, 256 or 512 cells (the next of these at or above nx), e.g. 288-cell rows
+ * 512 (1.78x) and 384-cell rows 512 (1.33x: a 384^3 MM FP32 state is 15.1 GB
+ * instead of 11.3 GB).  save_state / load_state copy the padded image, and
+ * the adjoint keeps its checkpoints in this form. */
 lbem_status lbem_state_size(const lbem_desc *desc, size_t *bytes);
 
 /* Create a lattice.
@@ -167,8 +180,10 @@ lbem_status lbem_add_point_current(lbem_lattice *lat, int32_t x, int32_t y, int3
  * E0, B0: host float [3].  z < 0 removes the source. */
 lbem_status lbem_set_plane_source(lbem_lattice *lat, int32_t z, const float *E0, const float *B0, double period);
 
-/* Probe series: every later step records E and B of the state it collides
- * (the fields reported at that time level) at the given cells into
+/* Probe series (the field time series at fixed points that the tests of
+ * Sections IV-A to IV-C measure): every later step records E and B of the
+ * state it collides (the fields reported at that time level) at the given
+ * cells into
  * series[row][k][0..5] = (Ex, Ey, Ez, Bx, By, Bz), FP64, with
  * row = (n - n_set) mod cap_rows where n_set is the time level at this call.
  * cells: host int64 [n]; series: dev double [cap_rows][n][6].  n = 0 disables.
@@ -189,10 +204,20 @@ lbem_status lbem_set_flux_monitor(lbem_lattice *lat, int32_t n, const int64_t *c
 
 /* Detector plane z (z < 0 disables): every later step adds the sum over the
  * plane of |E|^2 of the state it collides to an FP64 accumulator kept in the
- * workspace (deterministic order).  Setting the plane clears the accumulator. */
+ * workspace (deterministic order).  Setting the plane clears the accumulator.
+ * This is the loss of the inverse-design problem (the energy that reaches a
+ * plane); the paper measures transmitted fields at points behind the media
+ * (Sections IV-A, IV-D). */
 lbem_status lbem_set_detector(lbem_lattice *lat, int32_t z);
 /* Write the accumulated detector sum to out (dev double [1]). */
 lbem_status lbem_detector_read(lbem_lattice *lat, double *out);
+
+/* lbem_set_detector(z), and after every later lbem_step call the accumulated
+ * sum is also written to acc (dev double [1], owned by the caller, kept alive
+ * while the plane is set), which this call zeroes: one small extra launch per
+ * lbem_step call, not per step.  z < 0 disables (acc may then be NULL).
+ * lbem_set_detector and lbem_adjoint_forward drop acc. */
+lbem_status lbem_set_detector_plane(lbem_lattice *lat, int32_t z, double *acc);
 
 /* Energy series: every later step whose time level n satisfies
  * (n - n_set) mod every == 0 writes U = 1/2 sum (E.D + B.H) of the state it
@@ -212,8 +237,22 @@ lbem_status lbem_get_time(lbem_lattice *lat, int64_t *t);
  * HV: D and B are the moments, E = D / (eps0 eps_r), H = B / (mu0 mu_r). */
 lbem_status lbem_get_fields(lbem_lattice *lat, float *E, float *B, float *D, float *H);
 
-/* U = 1/2 sum over cells of (E.D + B.H) of the current state -> out (dev double [1]). */
+/* Field energy of Section I-B's linear media, U = 1/2 sum over cells of
+ * (E.D + B.H) with D = eps_r eps0 E and H = B / (mu_r mu0), of the current
+ * state -> out (dev double [1]).  FP64: per-block partials, then one
+ * deterministic pass. */
 lbem_status lbem_energy(lbem_lattice *lat, double *out);
+
+/* Failure detection: computes the energy of the current state (as
+ * lbem_energy) and, if a detector plane is set, its accumulated sum, waits
+ * for both (synchronises the stream) and returns
+ *   LBEM_ENOTFINITE if either is not finite (a NaN or infinity anywhere in
+ *     the populations reaches the energy);
+ *   LBEM_EUNSTABLE if max_energy > 0 and the energy exceeds it (growth: with
+ *     eps_r or mu_r varying in 2-D or 3-D, both schemes have growing modes);
+ *   LBEM_OK otherwise.  max_energy = 0 checks finiteness only.
+ * energy: host double [1] receiving the energy, or NULL. */
+lbem_status lbem_check(lbem_lattice *lat, double max_energy, double *energy);
 
 /* Launch tuning of the step kernel, per parity (index 0 even, 1 odd time
  * level).  form[p] = kernel + 4 * order:
@@ -264,6 +303,10 @@ lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t);
  * across segments.  Every model (LBEM_MM_DIFF gives the gradients of LBEM_MM
  * at 24 / 50 of the traffic); no soft or hard sources may be set.
  * ------------------------------------------------------------------------ */
+
+/* The adjoint needs FP32 population storage (LBEM_EINVAL otherwise): the
+ * reverse kernels differentiate the unrounded FP32 step, which is the forward
+ * map only when no population is rounded to 16 bits between steps. */
 
 /* Bytes of adjoint workspace for nsteps steps with a checkpoint every K steps,
  * of which the last `keep` segments (>= 1) also hold their per-step E frames

@@ -524,6 +524,7 @@ lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, i
     if (st) return st;
     if (!bytes) return fail(LBEM_EINVAL, "bytes is NULL");
     if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
+    if (desc->storage != LBEM_F32) return fail(LBEM_EINVAL, "the adjoint needs FP32 population storage");
     *bytes = adj_layout(desc, nsteps, K, keep).total;
     return LBEM_OK;
 }
@@ -532,6 +533,9 @@ lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, i
                                  size_t ws_bytes, double *loss) {
     if (!lat || !ws || !loss) return fail(LBEM_EINVAL, "null argument");
     if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
+    // the reverse kernels differentiate the unrounded FP32 step, which is the
+    // forward map only when nothing is rounded to 16 bits between steps
+    if (lat->d.storage != LBEM_F32) return fail(LBEM_EINVAL, "the adjoint needs FP32 population storage");
     if (lat->nsrc > 0 || lat->plane_z >= 0) return fail(LBEM_ESTATE, "the adjoint needs a lattice without sources");
     if (det_z < 0 || det_z >= lat->d.nz) return fail(LBEM_EINVAL, "detector plane z = %d outside the lattice", det_z);
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(LBEM_EINVAL, "workspace must be 256-byte aligned");

@@ -162,9 +162,11 @@ struct lbem_lattice {
     int32_t flx_n;
     int64_t flx_t0, flx_t1;
     double *flx_max;
-    // detector
+    // detector; det_acc: caller buffer that receives the accumulated sum after
+    // every lbem_step call (lbem_set_detector_plane), or null
     int32_t det_z;
     uint32_t det_b0, det_b1;
+    double *det_acc;
     // energy series
     int32_t en_every;
     int64_t en_cap, en_t0;

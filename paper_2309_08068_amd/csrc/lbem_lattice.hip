@@ -417,6 +417,11 @@ lbem_status lbem_workspace_size(const lbem_desc *desc, size_t *bytes) {
     return LBEM_OK;
 }
 
+size_t lbem_workspace_bytes(const lbem_desc *desc) {
+    size_t bytes = 0;
+    return lbem_workspace_size(desc, &bytes) == LBEM_OK ? bytes : 0;
+}
+
 lbem_status lbem_state_size(const lbem_desc *desc, size_t *bytes) {
     lbem_status st = check_desc(desc);
     if (st) return st;
@@ -729,6 +734,7 @@ lbem_status lbem_set_flux_monitor(lbem_lattice *lat, int32_t n, const int64_t *c
 lbem_status lbem_set_detector(lbem_lattice *lat, int32_t z) {
     if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
     if (z >= lat->d.nz) return fail(LBEM_EINVAL, "detector z = %d outside the lattice", z);
+    lat->det_acc = nullptr;
     if (z < 0) {
         lat->det_z = -1;
         return LBEM_OK;
@@ -750,6 +756,17 @@ lbem_status lbem_detector_read(lbem_lattice *lat, double *out) {
                        reinterpret_cast<const double *>(lat->ws + lat->L.det_part),
                        (lat->det_b1 - lat->det_b0 + 1) * kSegMax, out);
     return hip_check(hipGetLastError(), "detector sum");
+}
+
+lbem_status lbem_set_detector_plane(lbem_lattice *lat, int32_t z, double *acc) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (z >= 0 && !acc) return fail(LBEM_EINVAL, "acc is NULL");
+    lbem_status st = lbem_set_detector(lat, z);
+    if (st || z < 0) return st;
+    lat->det_acc = acc;
+    hipLaunchKernelGGL(zero_bytes, dim3(1), dim3(kBlock), 0, lat->stream, reinterpret_cast<uint32_t *>(acc),
+                       size_t(2));
+    return hip_check(hipGetLastError(), "zero detector accumulator");
 }
 
 lbem_status lbem_set_energy_series(lbem_lattice *lat, int32_t every, int64_t cap, double *series) {
@@ -924,6 +941,7 @@ lbem_status lbem::step_impl(lbem_lattice *lat, int64_t nsteps, float *frames) {
         if (st) return st;
         lat->t = t + 1;
     }
+    if (lat->det_acc && lat->det_z >= 0 && nsteps > 0) return lbem_detector_read(lat, lat->det_acc);
     return LBEM_OK;
 }
 
@@ -1038,6 +1056,30 @@ lbem_status lbem_energy(lbem_lattice *lat, double *out) {
     if (st) return st;
     hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, lat->stream, part, lat->nobs, out);
     return hip_check(hipGetLastError(), "energy sum");
+}
+
+lbem_status lbem_check(lbem_lattice *lat, double max_energy, double *energy) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (!(max_energy >= 0.0)) return fail(LBEM_EINVAL, "max_energy must be >= 0 (0: no bound)");
+    // the two FP64 results go to the flags block of the workspace (its first
+    // 16 bytes hold the media validation counts)
+    double *dev = reinterpret_cast<double *>(lat->ws + lat->L.flags + 16);
+    lbem_status st = lbem_energy(lat, dev);
+    if (!st && lat->det_z >= 0) st = lbem_detector_read(lat, dev + 1);
+    double host[2] = {0.0, 0.0};
+    if (!st) st = hip_check(hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, lat->stream), "copy check");
+    if (!st) st = hip_check(hipStreamSynchronize(lat->stream), "synchronise");
+    if (st) return st;
+    if (lat->det_z < 0) host[1] = 0.0;
+    if (energy) *energy = host[0];
+    if (!std::isfinite(host[0]))
+        return fail(LBEM_ENOTFINITE, "the field energy at time level %lld is not finite", (long long)lat->t);
+    if (!std::isfinite(host[1]))
+        return fail(LBEM_ENOTFINITE, "the detector sum at time level %lld is not finite", (long long)lat->t);
+    if (max_energy > 0.0 && host[0] > max_energy)
+        return fail(LBEM_EUNSTABLE, "the field energy %.6e at time level %lld exceeds the bound %.6e", host[0],
+                    (long long)lat->t, max_energy);
+    return LBEM_OK;
 }
 
 // state = populations, then (shifted storage) the record plane the next step reads

@@ -28,6 +28,7 @@ SIGNATURES = {
     "lbem_version": (_I32, []),
     "lbem_last_error": (C.c_char_p, []),
     "lbem_workspace_size": (_I32, [_P, C.POINTER(_SZ)]),
+    "lbem_workspace_bytes": (_SZ, [_P]),
     "lbem_state_size": (_I32, [_P, C.POINTER(_SZ)]),
     "lbem_create": (_I32, [_P, _P, _P, _P, _P, _SZ, _P, C.POINTER(_P)]),
     "lbem_destroy": (_I32, [_P]),
@@ -40,6 +41,8 @@ SIGNATURES = {
     "lbem_set_flux_monitor": (_I32, [_P, _I32, _P, _I64, _I64, _P]),
     "lbem_set_detector": (_I32, [_P, _I32]),
     "lbem_detector_read": (_I32, [_P, _P]),
+    "lbem_set_detector_plane": (_I32, [_P, _I32, _P]),
+    "lbem_check": (_I32, [_P, _D, C.POINTER(_D)]),
     "lbem_set_energy_series": (_I32, [_P, _I32, _I64, _P]),
     "lbem_step": (_I32, [_P, _I64]),
     "lbem_get_time": (_I32, [_P, C.POINTER(_I64)]),
@@ -238,6 +241,14 @@ class Lattice:
     def set_detector(self, z: int):
         check(self.lib.lbem_set_detector(self.h, int(z)))
 
+    def set_detector_plane(self, z: int) -> torch.Tensor:
+        """Detector plane whose accumulated sum the library writes to the
+        returned device tensor after every step call."""
+        acc = torch.empty(1, dtype=torch.float64, device=self.device)
+        check(self.lib.lbem_set_detector_plane(self.h, int(z), _ptr(acc)))
+        self._keep["detector_acc"] = acc
+        return acc
+
     def detector(self) -> torch.Tensor:
         out = torch.zeros(1, dtype=torch.float64, device=self.device)
         check(self.lib.lbem_detector_read(self.h, _ptr(out)))
@@ -273,6 +284,13 @@ class Lattice:
         out = torch.zeros(1, dtype=torch.float64, device=self.device)
         check(self.lib.lbem_energy(self.h, _ptr(out)))
         return out
+
+    def check(self, max_energy: float = 0.0) -> float:
+        """lbem_check: the energy of the current state; raises LbemError with
+        LBEM_ENOTFINITE or LBEM_EUNSTABLE (see include/lbem.h)."""
+        u = C.c_double()
+        check(self.lib.lbem_check(self.h, float(max_energy), C.byref(u)))
+        return u.value
 
     def state_size(self) -> int:
         out = C.c_size_t()

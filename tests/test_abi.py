@@ -164,3 +164,26 @@ def test_null_handles_rejected(lib):
     assert lib.lbem_destroy(None) == -1
     assert lib.lbem_get_fields(None, None, None, None, None) == -1
     assert lib.lbem_energy(None, None) == -1
+    assert lib.lbem_check(None, 0.0, None) == -1
+    assert lib.lbem_set_detector_plane(None, 3, None) == -1
+
+
+def test_workspace_bytes_equals_workspace_size(lib):
+    for model, shape, storage in (("mm", (16, 16, 16), "f32"), ("hv", (256, 20, 13), "bf16"),
+                                  ("mmd", (200, 9, 41), "bf16_shifted")):
+        st, size = ws(model, shape, storage)
+        d = lbem.desc(model, shape, storage)
+        assert st == 0 and lib.lbem_workspace_bytes(C.byref(d)) == size
+    d = lbem.desc("mm", (0, 4, 4))
+    assert lib.lbem_workspace_bytes(C.byref(d)) == 0 and lib.lbem_last_error()
+    assert lib.lbem_workspace_bytes(None) == 0
+
+
+def test_adjoint_needs_fp32_storage(lib):
+    out = C.c_size_t()
+    for storage in ("bf16", "f16", "bf16_shifted", "f16_shifted"):
+        d = lbem.desc("hv", (16, 16, 16), storage)
+        assert lib.lbem_adjoint_workspace_size(C.byref(d), 10, 2, 1, C.byref(out)) == -1
+        assert b"FP32" in lib.lbem_last_error()
+    d = lbem.desc("hv", (16, 16, 16))
+    assert lib.lbem_adjoint_workspace_size(C.byref(d), 10, 2, 1, C.byref(out)) == 0

@@ -18,21 +18,17 @@ import torch
 
 import oracle
 from paper_2309_08068_amd import inputs, lbem
+from parity import ELEM, TOL, check, check16, elem, floor_bounds, rel
+from test_oracle_physics import radiation_against_theory
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5
 MODELS = ["mm", "hv", "mmd"]
 
 
 def base(model):
     """The scheme whose oracle and workloads a model is checked against."""
     return "mm" if model == "mmd" else model
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def random_problem(model, shape, seed, n_src=3, plane=False):
@@ -111,7 +107,7 @@ def test_random_state_parity(model, shape, steps):
     g, _ = run_gpu(model, shape, p, steps)
     o = run_oracle(model, shape, p, steps)
     for k in "EBDH":
-        assert rel(g[k], o[k]) < TOL, (k, rel(g[k], o[k]))
+        check(g[k], o[k], what=k)
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -128,7 +124,7 @@ def test_point_currents_with_own_period_and_phase(model, shape):
     g, lat = run_gpu(model, shape, p, 23)
     o = run_oracle(model, shape, p, 23)
     for k in "EBDH":
-        assert rel(g[k], o[k]) < TOL, (k, rel(g[k], o[k]))
+        check(g[k], o[k], what=k)
     # the same cell twice, a cell outside the lattice and a bad period are rejected
     nx, ny, _ = shape
     c0 = int(cells[0])
@@ -157,7 +153,7 @@ def test_shifted_storage_random_state(model, shape, steps, storage):
     g, _ = run_gpu(model, shape, p, steps, storage=storage)
     o = run_oracle(model, shape, p, steps)
     for k in "EBDH":
-        assert rel(g[k], o[k]) < SHIFTED_BOUND[storage], (k, rel(g[k], o[k]))
+        check16(g[k], o[k], SHIFTED_BOUND[storage], what=k)
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -175,8 +171,11 @@ def test_shifted_storage_beats_plain_on_smooth_fields(model, plain, shifted, sca
         gs, _ = run_gpu(model, shape, p, 100, storage=shifted, scale=scale)
         for k in "EB":
             ep, es = rel(gp[k], o[k]), rel(gs[k], o[k])
-            print(f"{model} {shape} {k}: {plain} {ep:.3e}, {shifted} {es:.3e} ({ep / es:.1f}x)", flush=True)
+            mp, ms = elem(gp[k], o[k]), elem(gs[k], o[k])
+            print(f"{model} {shape} {k}: {plain} {ep:.3e} (max {mp:.3e}), {shifted} {es:.3e} (max {ms:.3e}) "
+                  f"({ep / es:.1f}x)", flush=True)
             assert es < 0.5 * ep, (shape, k, ep, es)
+            assert ms < 0.5 * mp, (shape, k, mp, ms)
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -193,7 +192,7 @@ def test_observations_parity(model, shape, tuning):
     probes = [0, 17, shape[0] * shape[1] * 7 + 5, n - 1]
     g, _ = run_gpu(model, shape, p, steps, probes=probes, det_z=6, energy_every=4, tuning=tuning)
     o = run_oracle(model, shape, p, steps, probes=probes, det_z=6, energy_every=4)
-    assert rel(g["probes"], o["probes"]) < TOL
+    check(g["probes"], o["probes"], what="probes")
     np.testing.assert_allclose(g["energy"], o["energy"], rtol=TOL)
     np.testing.assert_allclose(g["detector"][0], o["detector"].sum(), rtol=TOL)
 
@@ -206,9 +205,9 @@ def oracle_max_flux(model, series, mu_cells, n0, n1):
 
 
 @pytest.mark.parametrize("model", MODELS)
-@pytest.mark.parametrize("shape,storage,tol", [((12, 10, 14), "f32", TOL), ((128, 6, 14), "f32", TOL),
-                                               ((128, 6, 14), "bf16_shifted", 3e-2)])
-def test_flux_monitor_parity(model, shape, storage, tol):
+@pytest.mark.parametrize("shape,storage,tol,etol", [((12, 10, 14), "f32", TOL, ELEM), ((128, 6, 14), "f32", TOL, ELEM),
+                                                    ((128, 6, 14), "bf16_shifted", 3e-2, 6e-2)])
+def test_flux_monitor_parity(model, shape, storage, tol, etol):
     """lbem_set_flux_monitor on a random state with soft currents: the largest
     |E x H| per monitored cell over a window of time levels, against the same
     maximum taken from the oracle's FP64 probe series; the maxima keep folding
@@ -227,9 +226,8 @@ def test_flux_monitor_parity(model, shape, storage, tol):
     torch.cuda.synchronize()
     o = run_oracle(model, shape, p, steps, probes=list(cells))
     ref = oracle_max_flux(model, o["probes"], p["mu"][cells], n0, n1)
-    err = rel(flux.cpu().numpy(), ref)
-    print(f"{model} {shape} {storage}: flux maxima rel err {err:.2e}", flush=True)
-    assert err < tol
+    err, emax = check(flux.cpu().numpy(), ref, tol, etol, "flux maxima")
+    print(f"{model} {shape} {storage}: flux maxima rel err {err:.2e}, element-wise {emax:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -247,39 +245,77 @@ def test_radiation_workload_parity(model):
     p = dict(eps=None, mu=None, sig=w.sigma, E0=w.fields0()[0], B0=w.fields0()[1], currents=w.currents)
     o = run_oracle(model, w.shape, p, w.steps, probes=list(rad.cells))
     ref = oracle_max_flux(model, o["probes"], np.ones(len(rad.cells)), *rad.window)
-    err = rel(flux.cpu().numpy(), ref)
-    print(f"{model} radiation 96^3: flux maxima rel err {err:.2e}", flush=True)
-    assert err < TOL
+    err, emax = check(flux.cpu().numpy(), ref, what="flux maxima")
+    print(f"{model} radiation 96^3: flux maxima rel err {err:.2e}, element-wise {emax:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("model", MODELS)
 def test_radiation_pattern_full_size(model):
     """The radiation pattern at 256^3 (R = 37 cells, one period after the
     front has passed R by a wavelength): r^2 times the largest flux follows
-    sin^2(theta) on four azimuths, and its equatorial value matches a Hertz
-    dipole of moment sum(J) / omega (peak far-field flux mu0 omega^4 p^2 /
-    (16 pi^2 c)) within 10 %: at k R = 5.1 the instantaneous flux still holds
-    near-field terms of relative size O(1 / (k R)^2), about 4 % (measured:
-    MM 0.997-1.028, HV 1.010-1.052)."""
+    sin^2(theta) on four azimuths; the largest flux of every sample cell with
+    sin(theta) > 0.5 is compared with that of the continuum fields of the same
+    source (dipoles switched on at t = 0, with the static moment, the
+    near-field terms at k R = 5.1 and the source's extent).  Their mean ratio
+    must be within (k dx)^2 = 0.019 of 1, the order of the scheme's
+    discretisation error at k dx = 0.139, and every cell within 0.05: the
+    maximum falls at the start of the window, right behind the switched-on
+    front, whose lattice dispersion leaves a per-cell scatter that does not
+    shrink as fast (measured over n = 96 .. 384, where the mean converges)."""
     rad = inputs.radiation(base(model), n=256)
     w = rad.workload
     lat = lbem.lattice_from_workload(w, model=model)
     lat.autotune(2)
     flux = lat.set_flux_monitor(rad.cells, *rad.window)
     lat.step(w.steps)
-    smax = flux.cpu().numpy() * rad.radius ** 2
-    pattern = smax / smax.max()
+    smax = flux.cpu().numpy()
+    pattern = smax * rad.radius ** 2 / (smax * rad.radius ** 2).max()
     perr = np.abs(pattern - np.sin(rad.theta) ** 2).max()
-    om = 2 * math.pi / rad.period
-    pm = sum(c[1][2] for c in w.currents) / om
-    c0 = inputs.VACUUM_SPEED[base(model)]
-    theory = inputs.VACUUM_CONSTANTS[base(model)][1] * om ** 4 * pm ** 2 / (16 * math.pi ** 2 * c0)
-    eq = np.abs(rad.theta - math.pi / 2) < 0.3
-    ratio = smax[eq] / (theory * np.sin(rad.theta[eq]) ** 2)
-    print(f"{model} radiation 256^3: pattern max deviation {perr:.4f}, equatorial flux / theory "
-          f"{ratio.min():.3f}..{ratio.max():.3f}", flush=True)
+    ratio, bound = radiation_against_theory(base(model), rad, smax)
+    print(f"{model} radiation 256^3: pattern max deviation {perr:.4f}, flux / continuum mean {ratio.mean():.4f}, "
+          f"cells {ratio.min():.4f}..{ratio.max():.4f} (bounds {bound:.4f}, 0.05)", flush=True)
     assert perr < 0.06
-    assert np.all((ratio > 0.9) & (ratio < 1.1))
+    assert abs(ratio.mean() - 1) < bound
+    assert np.all(np.abs(ratio - 1) < 0.05)
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_point_dipole_far_field(model):
+    """The benchmark's point dipole (256^3, J_z = sin(2 pi n / 40) in one cell,
+    1000 steps) against the far field of a Hertz dipole of moment 1 / omega:
+    |E_theta| = mu0 omega / (4 pi r) at r = 60 on the equator, 6.25e-4 for HV
+    and 4.17e-4 for MM (Section IV-C; near-field terms at k r = 28 and 13 add
+    0.1 % and 0.6 %), taken at the centres of the blocks below (r = 61.5).  A one-cell source also feeds grid-scale modes that the
+    tau = 1/2 collision never damps, and for MM it drives only one of the two
+    sublattices that face-diagonal velocities keep apart, so single cells
+    read 0 or about twice the field.  The comparison therefore uses the mean
+    of E_z over a 4 x 4 x 4 block of cells at each of the four equatorial
+    points (measured over the last period), divided by the block mean's own
+    attenuation of a wave along the axis, |sin(2k) / (4 sin(k/2))|.  HV must
+    be within (k dx)^2 = 0.22 (k dx = 0.47; measured 1.05); MM (k dx = 0.22)
+    is printed, not bounded (measured 0.95: see the design notes)."""
+    w = inputs.dipole(base(model), n=256, steps=1000)
+    n, r, T = 256, 60, 40
+    c = n // 2
+    corners = [(c + r, c, c), (c, c + r, c), (c - r - 3, c, c), (c, c - r - 3, c)]
+    pts = [(x + i, y + j, z + k - 2) for (x, y, z) in corners for k in range(4) for j in range(4) for i in range(4)]
+    lat = lbem.lattice_from_workload(w, model=model)
+    lat.autotune(2)
+    series = lat.set_probes([inputs.cell_index(w.shape, *p) for p in pts], w.steps)
+    lat.step(w.steps)
+    ez = series.cpu().numpy()[w.steps - T:, :, 2].reshape(T, 4, 64)
+    eps0, mu0 = inputs.VACUUM_CONSTANTS[base(model)]
+    om = 2 * np.pi / T
+    k = om / inputs.VACUUM_SPEED[base(model)]
+    far = mu0 * om / (4 * np.pi * (r + 1.5))  # at the blocks' centres
+    att = abs(np.sin(2 * k) / (4 * np.sin(k / 2)))
+    amp = np.abs(ez.mean(axis=2)).max(axis=0) / att
+    ratio = amp / far
+    print(f"{model} point dipole 256^3, 1000 steps: block-mean |E_theta| at r = 60 over the Hertz value {far:.4e}: "
+          + " ".join(f"{x:.4f}" for x in ratio), flush=True)
+    assert np.isfinite(ratio).all()
+    if base(model) == "hv":
+        assert np.all(np.abs(ratio - 1) < k * k)
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -294,9 +330,10 @@ def test_energy_call_matches_oracle(model, shape):
 
 
 def float_floor(model, shape, p, steps):
+    """The FP64 oracle run and the bounds from its float32 build's drift."""
     o64 = run_oracle(model, shape, p, steps)
     o32 = run_oracle(model, shape, p, steps, real="f32")
-    return max(rel(o32[k], o64[k]) for k in "EB"), o64
+    return floor_bounds([o32[k] for k in "EB"], [o64[k] for k in "EB"]), o64
 
 
 @pytest.mark.parametrize("model,steps", [("mm", 2000), ("hv", 1000), ("mmd", 2000)])
@@ -308,14 +345,14 @@ def test_interface_workload_parity(model, steps):
     steps, so HV is compared over the first 1000 steps."""
     w = inputs.interface(base(model), steps=steps)
     p = dict(eps=w.eps_r, mu=w.mu_r, sig=None, E0=w.E0, B0=w.B0)
-    floor, o = float_floor(model, w.shape, p, w.steps)
+    (tol, etol, fr, fe), o = float_floor(model, w.shape, p, w.steps)
     g, _ = run_gpu(model, w.shape, p, w.steps)
-    tol = max(TOL, 2 * floor)
-    errs = {k: rel(g[k], o[k]) for k in "EB"}
-    print(f"{model} interface {steps} steps: float32 floor {floor:.2e}, tolerance {tol:.2e}, errors {errs}",
+    errs = {k: (rel(g[k], o[k]), elem(g[k], o[k])) for k in "EB"}
+    print(f"{model} interface {steps} steps: float32 floor {fr:.2e} (element-wise {fe:.2e}), bounds {tol:.2e} / "
+          f"{etol:.2e}, GPU errors (L2, element-wise) " + ", ".join(f"{k} {a:.2e} {b:.2e}" for k, (a, b) in errs.items()),
           flush=True)
     for k in "EB":
-        assert errs[k] < tol, (k, errs[k])
+        check(g[k], o[k], tol, etol, k)
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -324,12 +361,14 @@ def test_skin_workload_parity(model):
     w = inputs.skin(base(model))
     E0, B0 = w.fields0()
     p = dict(eps=None, mu=None, sig=w.sigma, E0=E0, B0=B0, plane=w.plane)
-    floor, o = float_floor(model, w.shape, p, w.steps)
+    (tol, etol, fr, fe), o = float_floor(model, w.shape, p, w.steps)
     g, _ = run_gpu(model, w.shape, p, w.steps)
-    tol = max(TOL, 2 * floor)
-    print(f"{model} skin: float32 floor {floor:.2e}, tolerance {tol:.2e}", flush=True)
+    errs = {k: (rel(g[k], o[k]), elem(g[k], o[k])) for k in "EB"}
+    print(f"{model} skin: float32 floor {fr:.2e} (element-wise {fe:.2e}), bounds {tol:.2e} / {etol:.2e}, "
+          "GPU errors (L2, element-wise) " + ", ".join(f"{k} {a:.2e} {b:.2e}" for k, (a, b) in errs.items()),
+          flush=True)
     for k in "EB":
-        assert rel(g[k], o[k]) < tol, (k, rel(g[k], o[k]))
+        check(g[k], o[k], tol, etol, k)
 
 
 @pytest.fixture(scope="module")
@@ -361,7 +400,11 @@ def test_dipole_full_size_parity(dipole_oracle, model, storage, tol):
     torch.cuda.synchronize()
     g = dict(E=E.double().cpu().numpy(), B=B.double().cpu().numpy(), probes=series.cpu().numpy())
     for k in ("E", "B", "probes"):
-        assert rel(g[k], o[k]) < tol, (k, rel(g[k], o[k]))
+        if storage == "f32":
+            er, ee = check(g[k], o[k], what=k)
+        else:
+            er, ee = check16(g[k], o[k], tol, what=k)
+        print(f"{model} {storage} 256^3 {k}: relative L2 {er:.2e}, element-wise {ee:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -432,13 +475,17 @@ def test_dipole_384_properties(dipole384_f32, model, storage):
     E32, B32 = dipole384_f32(model, steps)
     dE = ((E - E32).norm() / E32.norm()).item()
     dB = ((B - B32).norm() / B32.norm()).item()
-    print(f"{model} {storage} 384^3: asymmetry {asym:.2e}, distance from FP32 storage E {dE:.2e} B {dB:.2e}",
-          flush=True)
+    mE = ((E - E32).abs().max() / E32.abs().max()).item()
+    mB = ((B - B32).abs().max() / B32.abs().max()).item()
+    print(f"{model} {storage} 384^3: asymmetry {asym:.2e}, distance from FP32 storage E {dE:.2e} B {dB:.2e}, "
+          f"element-wise E {mE:.2e} B {mB:.2e}", flush=True)
     assert asym <= (1e-4 if storage == "f32" else 2e-2)
     if storage == "f32":
         assert dE == 0.0 and dB == 0.0  # every launch choice gives the same bits
     else:
-        assert dE < DIPOLE384_BOUND[storage] and dB < DIPOLE384_BOUND[storage]
+        bound = DIPOLE384_BOUND[storage]
+        assert dE < bound and dB < bound
+        assert mE <= 2 * bound and mB <= 2 * bound
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -481,7 +528,64 @@ def test_low_precision_storage_bound(model, storage, bound):
         g, _ = run_gpu(model, shape, p, 100, storage=storage, scale=256.0 if storage == "f16" else 0.0)
         o = run_oracle(model, shape, p, 100)
         for k in "EB":
-            assert rel(g[k], o[k]) < bound, (shape, k, rel(g[k], o[k]))
+            check16(g[k], o[k], bound, what=f"{shape} {k}")
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_detector_plane_accumulator(model):
+    """lbem_set_detector_plane: the caller's accumulator holds the detector
+    sum after every step call (two calls here), equal to the oracle's."""
+    shape = (128, 6, 14)
+    p = random_problem(model, shape, seed=12)
+    lat = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"])
+    lat.set_fields(p["E0"], p["B0"])
+    lat.set_currents(p["currents"])
+    acc = lat.set_detector_plane(6)
+    lat.step(7)
+    torch.cuda.synchronize()
+    first = acc.item()
+    lat.step(6)
+    torch.cuda.synchronize()
+    o = run_oracle(model, shape, p, 13, det_z=6)
+    np.testing.assert_allclose(first, o["detector"][:7].sum(), rtol=TOL)
+    np.testing.assert_allclose(acc.item(), o["detector"].sum(), rtol=TOL)
+    assert acc.item() == lat.detector().item()
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_check_flags_non_finite_and_growth(model):
+    """lbem_check (failure detection): a finite state passes and returns the
+    energy lbem_energy gives; an energy above the caller's bound is
+    LBEM_EUNSTABLE; infinite initial fields (non-finite floats all the way
+    through, no fault) are LBEM_ENOTFINITE, from the energy and, with the
+    field energy still finite, from the detector sum."""
+    shape = (16, 12, 10)
+    p = random_problem(model, shape, seed=8)
+    lat = lbem.Lattice(model, shape, p["eps"], p["mu"], p["sig"])
+    lat.set_fields(p["E0"], p["B0"])
+    lat.set_detector(4)
+    lat.step(5)
+    u = lat.check()
+    assert u == lat.energy().item() and math.isfinite(u) and u > 0
+    assert lat.check(2 * u) == u
+    with pytest.raises(lbem.LbemError) as e:
+        lat.check(0.5 * u)
+    assert e.value.status == -4
+    E0 = p["E0"].copy()
+    E0[0, 4 * 16 * 12 + 17] = np.inf  # a cell of the detector plane z = 4
+    lat.set_fields(E0, p["B0"])
+    lat.step(3)
+    with pytest.raises(lbem.LbemError) as e:
+        lat.check()
+    assert e.value.status == -6
+    # a non-finite detector sum alone: the plane's sum saw the infinite
+    # fields, then the fields are reset to finite ones without clearing it
+    lat.set_fields(p["E0"], p["B0"])
+    with pytest.raises(lbem.LbemError) as e:
+        lat.check()
+    assert e.value.status == -6 and "detector" in str(e.value)
+    lat.set_detector(4)
+    assert math.isfinite(lat.check())
 
 
 def test_unstable_and_invalid_media_rejected():

@@ -19,6 +19,7 @@ import torch
 
 import oracle
 from paper_2309_08068_amd import inputs, lbem
+from parity import elem, floor_bounds, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -29,10 +30,6 @@ N64 = 64
 # keeps 8 significand bits, FP16 (scale 1024) 11
 BOUNDS = {"bf16": 0.3, "f16": 0.05, "bf16_shifted": 0.3, "f16_shifted": 0.05}
 PLAIN = {"bf16_shifted": "bf16", "f16_shifted": "f16"}
-
-
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def oracle_fields(w, real):
@@ -56,21 +53,41 @@ def gpu_errors(w, ref64, cache, storage):
         lat.step(w.steps)
         E, B, _, _ = lat.fields()
         torch.cuda.synchronize()
-        cache[storage] = (rel(E.double().cpu().numpy(), ref64[0]), rel(B.double().cpu().numpy(), ref64[1]))
+        E, B = E.double().cpu().numpy(), B.double().cpu().numpy()
+        far = away_from_source(w)
+        cache[storage] = (rel(E, ref64[0]), rel(B, ref64[1]), elem(E[:, far], ref64[0][:, far]),
+                          elem(B[:, far], ref64[1][:, far]), elem(E, ref64[0]), elem(B, ref64[1]))
     return cache[storage]
+
+
+def away_from_source(w, r_min=4.0):
+    """Cells at least r_min from the point source.  At the source cell and its
+    neighbours the populations are the largest of the lattice and the 16-bit
+    rounding of each is of the order of the fields there, so the element-wise
+    bound, which assumes errors spread over the lattice, is taken outside."""
+    nx, ny, nz = w.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - nx // 2) ** 2 + (y - ny // 2) ** 2 + (z - nz // 2) ** 2).reshape(-1)
+    return r >= r_min
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "bf16_shifted", "f16_shifted"])
 def test_precision_sweep(reference, storage):
     w, ref, cache = reference
-    E64, B64 = ref["f64"]
-    floor = max(rel(ref["f32"][0], E64), rel(ref["f32"][1], B64))
-    eE, eB = gpu_errors(w, ref["f64"], cache, storage)
-    print(f"{w.model} {storage}: rel L2 E {eE:.3e} B {eB:.3e} (float32 oracle floor {floor:.3e})", flush=True)
-    bound = max(1e-5, 2 * floor) if storage == "f32" else BOUNDS[storage]
+    tol, etol, fr, fe = floor_bounds(ref["f32"], ref["f64"])
+    eE, eB, mE, mB, aE, aB = gpu_errors(w, ref["f64"], cache, storage)
+    print(f"{w.model} {storage}: rel L2 E {eE:.3e} B {eB:.3e}, element-wise (r >= 4) E {mE:.3e} B {mB:.3e}, "
+          f"(all cells) E {aE:.3e} B {aB:.3e} (float32 oracle floor {fr:.3e}, element-wise {fe:.3e})", flush=True)
+    if storage == "f32":
+        mE, mB = aE, aB
+    if storage == "f32":
+        bound, ebound = tol, etol
+    else:
+        bound, ebound = BOUNDS[storage], 2 * BOUNDS[storage]
     assert eE < bound and eB < bound
+    assert mE <= ebound and mB <= ebound
     if storage in PLAIN:
-        pE, pB = gpu_errors(w, ref["f64"], cache, PLAIN[storage])
+        pE, pB = gpu_errors(w, ref["f64"], cache, PLAIN[storage])[:2]
         print(f"{w.model} {storage}: {pE / eE:.2f}x (E) and {pB / eB:.2f}x (B) below {PLAIN[storage]}", flush=True)
         assert eE <= 1.05 * pE and eB <= 1.05 * pB
 
@@ -81,8 +98,8 @@ def test_shifted_storage_gain_with_gaussian_source(model):
     ref64 = oracle_fields(w, "f64")
     cache = {}
     for shifted, plain in PLAIN.items():
-        eE, eB = gpu_errors(w, ref64, cache, shifted)
-        pE, pB = gpu_errors(w, ref64, cache, plain)
+        eE, eB = gpu_errors(w, ref64, cache, shifted)[:2]
+        pE, pB = gpu_errors(w, ref64, cache, plain)[:2]
         print(f"{model} gaussian source: {plain} {pE:.3e}/{pB:.3e}, {shifted} {eE:.3e}/{eB:.3e} "
               f"({pE / eE:.1f}x, {pB / eB:.1f}x)", flush=True)
         assert eE < 0.5 * pE and eB < 0.5 * pB
