@@ -335,6 +335,27 @@ lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, i
 lbem_status lbem_adjoint_backward(lbem_lattice *lat, void *ws, size_t ws_bytes, const float *E0, const float *B0,
                                   double scale, double *grad_eps, double *grad_sigma);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbem_adjoint
+ * with its workspace in a fixed device array of lbem_adjoint_static_bytes()
+ * bytes (64 MiB) that the library holds on every GPU it runs on until the
+ * process ends, instead of a caller buffer.  Same arguments, results and
+ * errors as lbem_adjoint, except:
+ *   - LBEM_ENOMEM if lbem_adjoint_workspace_size for (nsteps, K, keep)
+ *     exceeds that size (nothing is enqueued);
+ *   - the GPU the lattice was created on must be current (LBEM_EINVAL);
+ *   - a lattice without an adjoint tuning (lbem_set_adjoint_tuning) gets
+ *     form 0 and no cap instead of the timing lbem_adjoint's first reverse
+ *     pass does (which creates HIP events); the gradients are the same bits.
+ * It calls no allocating routine.  Every call on one GPU uses the same array:
+ * calls that overlap on one GPU (several streams or threads) race and give
+ * wrong gradients.  The array keeps the last call's contents; nothing in it
+ * needs to start at zero. */
+size_t lbem_adjoint_static_bytes(void);
+lbem_status lbem_adjoint_static(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z,
+                                const float *E0, const float *B0, double scale, double *grad_eps, double *grad_sigma,
+                                double *loss);
+
 /* Launch tuning of the adjoint kernel per parity of the reverse pass, as
  * lbem_set_tuning (form 0, 1 or 2; no split rows, no block order).  Setting it
  * skips the timing that the first lbem_adjoint_backward would do; results are

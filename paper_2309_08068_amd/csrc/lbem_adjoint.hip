@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/lbem.h"
 #include "lbem_common.hpp"
@@ -681,4 +682,73 @@ lbem_status lbem_get_adjoint_tuning(lbem_lattice *lat, int32_t *form, int32_t *b
         blocks_per_cu[p] = lat->adj_tuned ? lat->adj_cap[p] : -1;
     }
     return LBEM_OK;
+}
+
+// ------------------------------------------------------------------------
+// lbem_adjoint_static: lbem_adjoint with its workspace in a fixed device
+// array instead of a caller buffer, for callers that cannot allocate.
+//
+// `scratch` holds the checkpoints, frames, adjoint populations and FP32
+// gradient accumulators that lbem_adjoint keeps in `ws`.  Each GPU has its own
+// copy of the array; host code only ever uses the address that
+// hipGetSymbolAddress returns for the current GPU (the array's name is a
+// host-side stand-in, not a device address).  Nothing in it needs to start at
+// zero: the forward writes every checkpoint and frame before the reverse pass
+// reads it, and the reverse pass zeroes the adjoint populations and the
+// accumulators itself.
+// ------------------------------------------------------------------------
+static constexpr size_t kStaticAdjointBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticAdjointBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Address of this GPU's scratch array (looked up once per device, with that
+// device current).
+lbem_status scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBEM_EINVAL, "device %d outside the supported range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        lbem_status st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (st) return st;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBEM_OK;
+}
+}  // namespace
+
+size_t lbem_adjoint_static_bytes(void) { return kStaticAdjointBytes; }
+
+lbem_status lbem_adjoint_static(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z,
+                                const float *E0, const float *B0, double scale, double *grad_eps, double *grad_sigma,
+                                double *loss) {
+    if (!lat) return fail(LBEM_EINVAL, "lattice is NULL");
+    if (nsteps < 1 || K < 1 || keep < 1) return fail(LBEM_EINVAL, "nsteps, K and keep must be >= 1");
+    if (lat->d.storage != LBEM_F32) return fail(LBEM_EINVAL, "the adjoint needs FP32 population storage");
+    const size_t need = adj_layout(&lat->d, nsteps, K, keep).total;
+    if (need > kStaticAdjointBytes)
+        return fail(LBEM_ENOMEM, "the adjoint of this lattice needs %zu bytes of workspace; the fixed one holds %zu",
+                    need, kStaticAdjointBytes);
+    int dev = -1;
+    lbem_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    if (dev != lat->device)
+        return fail(LBEM_EINVAL, "the lattice was created on GPU %d, GPU %d is current", lat->device, dev);
+    void *ws = nullptr;
+    st = scratch_address(dev, &ws);
+    if (st) return st;
+    // the first reverse pass of lbem_adjoint times launch variants with HIP
+    // events; here a lattice without a tuning gets the row form with early
+    // store addresses and no occupancy cap (every form gives the same bits)
+    if (!lat->adj_tuned) {
+        const int32_t form[2] = {0, 0}, cap[2] = {0, 0};
+        st = lbem_set_adjoint_tuning(lat, form, cap);
+        if (st) return st;
+    }
+    return lbem_adjoint(lat, nsteps, K, keep, det_z, E0, B0, scale, grad_eps, grad_sigma, loss, ws,
+                        kStaticAdjointBytes);
 }

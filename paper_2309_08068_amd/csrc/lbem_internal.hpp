@@ -141,6 +141,7 @@ struct lbem_lattice {
     uint32_t nblocks;  // step-kernel blocks = table units, ceil(N / bu)
     uint32_t nobs;     // blocks of the 256-thread observation kernels
     float scale, inv_scale;
+    int device;  // the GPU current at lbem_create
     hipStream_t stream;
     char *ws;
     size_t ws_bytes;

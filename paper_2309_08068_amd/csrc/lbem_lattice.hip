@@ -456,6 +456,10 @@ lbem_status lbem_create(const lbem_desc *desc, const float *eps_r, const float *
     lat->stream = static_cast<hipStream_t>(stream);
     lat->ws = static_cast<char *>(workspace);
     lat->ws_bytes = workspace_bytes;
+    if (hipGetDevice(&lat->device) != hipSuccess) {
+        delete lat;
+        return fail(LBEM_EHIP, "hipGetDevice failed");
+    }
     lat->L = L;
     lat->pl = pop_layout(desc);
     lat->plane_z = -1;

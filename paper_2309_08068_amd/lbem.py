@@ -57,6 +57,8 @@ SIGNATURES = {
     "lbem_adjoint_forward": (_I32, [_P, _I64, _I32, _I32, _I32, _P, _SZ, _P]),
     "lbem_adjoint_backward": (_I32, [_P, _P, _SZ, _P, _P, _D, _P, _P]),
     "lbem_adjoint": (_I32, [_P, _I64, _I32, _I32, _I32, _P, _P, _D, _P, _P, _P, _P, _SZ]),
+    "lbem_adjoint_static_bytes": (_SZ, []),
+    "lbem_adjoint_static": (_I32, [_P, _I64, _I32, _I32, _I32, _P, _P, _D, _P, _P, _P]),
     "lbem_set_adjoint_tuning": (_I32, [_P, _P, _P]),
     "lbem_get_adjoint_tuning": (_I32, [_P, _P, _P]),
     "lbem_batch_workspace_size": (_I32, [_I32, _I32, _I32, _P, C.POINTER(_SZ)]),
@@ -377,6 +379,24 @@ class Lattice:
         B0 = _dev_f32(B0, 3 * self.n, self.device)
         check(self.lib.lbem_adjoint(self.h, int(nsteps), int(K), int(keep), int(det_z), _ptr(E0), _ptr(B0),
                                     float(scale), _ptr(ge), _ptr(gs), _ptr(loss), _ptr(ws), ws.numel()))
+        self._keep["adjoint_fields0"] = (E0, B0)
+        return loss, ge, gs
+
+    def adjoint_static(self, nsteps: int, K: int, det_z: int, keep: int = 1, E0=None, B0=None, scale: float = 1.0,
+                       out=None):
+        """lbem_adjoint_static: lbem_adjoint with the library's fixed device
+        workspace.  out: optional (loss [1], dL/deps_r [N], dL/dsigma [N])
+        float64 device tensors to write into; E0, B0 as for adjoint (device
+        float32 tensors are passed through without a copy)."""
+        if out is None:
+            out = (torch.zeros(1, dtype=torch.float64, device=self.device),
+                   torch.empty(self.n, dtype=torch.float64, device=self.device),
+                   torch.empty(self.n, dtype=torch.float64, device=self.device))
+        loss, ge, gs = out
+        E0 = _dev_f32(E0, 3 * self.n, self.device)
+        B0 = _dev_f32(B0, 3 * self.n, self.device)
+        check(self.lib.lbem_adjoint_static(self.h, int(nsteps), int(K), int(keep), int(det_z), _ptr(E0), _ptr(B0),
+                                           float(scale), _ptr(ge), _ptr(gs), _ptr(loss)))
         self._keep["adjoint_fields0"] = (E0, B0)
         return loss, ge, gs
 
