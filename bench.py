@@ -182,17 +182,47 @@ def time_batch(steps: int):
                                  "frac": round(mlups * 1e6 * VALU_PER_LU_BATCH / VALU_LANE_PEAK, 4)}}
 
 
-def time_adjoint(model: str, steps: int, K: int, keep: int):
+def time_adjoint(model: str, steps: int, K: int, keep: int, forward_model: str = None):
     """Inverse-design lattice 128 x 128 x 256 (FP32): adjoint pass (forward with
     a checkpoint every K steps, the last `keep` segments also keeping their E
-    frames, + reverse pass) over the plain forward with the same detector."""
+    frames, + reverse pass) over the plain forward of `forward_model` (default:
+    the same model) with the same detector.  Also reports the loss, the energy
+    of the forward run relative to the initial pulse (largest and last, from
+    an energy series every 50 steps: growth shows here) and lbem_check's
+    verdict on the final state."""
     import torch
     from paper_2309_08068_amd import inputs, lbem
 
+    fmodel = forward_model or model
     w = inputs.slab(workload_model(model), steps=steps)
+
+    def plain_forward():
+        lat = lbem.lattice_from_workload(w, model=fmodel)
+        lat.autotune(5)
+        lat.set_fields(*w.fields0())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        fwd = time.perf_counter() - t0
+        # untimed: the energy history of the same run
+        lat.set_fields(*w.fields0())
+        u0 = lat.energy().item()
+        series = lat.set_energy_series(50, (steps + 49) // 50)
+        lat.step(steps)
+        try:
+            # no sources: the pulse's energy can only fall (the sponges absorb)
+            lat.check(2.0 * u0)
+            health = "ok"
+        except lbem.LbemError as e:
+            health = lbem.STATUS.get(e.status, str(e.status))
+        u = series.cpu().numpy()
+        del lat
+        return fwd, u0, u, health
+
+    fwd, u0, u, health = plain_forward()
     lat = lbem.lattice_from_workload(w, model=model)
-    lat.autotune(5)
-    lat.step(5)
+    lat.autotune(5)  # the recomputed segments use the step kernel's tuning
     # a short adjoint pass lets the library pick its adjoint launch tuning
     # (once per lattice) before anything is timed
     lat.set_fields(*w.fields0())
@@ -201,35 +231,41 @@ def time_adjoint(model: str, steps: int, K: int, keep: int):
     lat.adjoint_backward(ws, *w.fields0())
     del ws
     lat.set_fields(*w.fields0())
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat.step(steps)
-    torch.cuda.synchronize()
-    fwd = time.perf_counter() - t0
-    lat.set_fields(*w.fields0())
     ws = lat.adjoint_workspace(steps, K, keep)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    lat.adjoint_forward(steps, K, w.det_z, ws, keep)
+    loss = lat.adjoint_forward(steps, K, w.det_z, ws, keep)
     ge, gs = lat.adjoint_backward(ws, *w.fields0())
     torch.cuda.synchronize()
     adj = time.perf_counter() - t1
     ok = bool(torch.isfinite(ge).all() and torch.isfinite(gs).all())
-    del ws
+    out = {"model": model, "forward_model": fmodel, "keep": keep, "forward_s": round(fwd, 4),
+           "adjoint_total_s": round(adj, 4), "ratio": round(adj / fwd, 3), "loss": float(f"{loss.item():.6e}"),
+           "grad_eps_max": float(f"{ge.abs().max().item():.4e}"), "finite_gradients": ok,
+           "energy_max_over_initial": round(float(u.max() / u0), 4),
+           # first time level (every 50) whose energy exceeds the initial one
+           "growth_from_step": next((50 * i for i, x in enumerate(u) if x > u0 * (1 + 1e-6)), None),
+           "energy_last_over_initial": round(float(u[-1] / u0), 4), "check": health,
+           "workspace_gb": round(ws.numel() / 1e9, 2)}
+    del ws, lat
     torch.cuda.empty_cache()
-    return {"workload": f"slab_128x128x256_{model}_{steps}steps_K{K}_keep{keep}", "forward_s": round(fwd, 4),
-            "adjoint_total_s": round(adj, 4), "ratio": round(adj / fwd, 3), "finite_gradients": ok}
+    return out
 
 
 def radiation_pattern(model: str, n: int):
     """Section IV-C radiation pattern at n^3: Gaussian dipole, flux monitor on a
     sphere of radius R; deviation of the normalised r^2 max|E x H| from
-    sin^2(theta), and the equatorial flux over the Hertz-dipole value."""
+    sin^2(theta), and the largest flux per sample cell over that of the
+    continuum fields of the same source (tests/dipole_theory.py: switched-on
+    dipoles with their static moment, near-field terms and extent)."""
     import math
 
     import numpy as np
     import torch
     from paper_2309_08068_amd import inputs, lbem
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import dipole_theory
 
     rad = inputs.radiation(workload_model(model), n=n)
     w = rad.workload
@@ -241,20 +277,22 @@ def radiation_pattern(model: str, n: int):
     lat.step(w.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    smax = flux.cpu().numpy() * rad.radius ** 2
-    pattern = smax / smax.max()
-    om = 2 * math.pi / rad.period
-    pm = sum(c[1][2] for c in w.currents) / om
+    smax = flux.cpu().numpy()
+    pattern = smax * rad.radius ** 2 / (smax * rad.radius ** 2).max()
     wm = workload_model(model)
-    theory = inputs.VACUUM_CONSTANTS[wm][1] * om ** 4 * pm ** 2 / (16 * math.pi ** 2 * inputs.VACUUM_SPEED[wm])
-    eq = np.abs(rad.theta - math.pi / 2) < 0.3
-    ratio = smax[eq] / (theory * np.sin(rad.theta[eq]) ** 2)
+    eps0, mu0 = inputs.VACUUM_CONSTANTS[wm]
+    om = 2 * math.pi / rad.period
+    theory = dipole_theory.max_flux(dipole_theory.workload_sources(w.shape, w.currents),
+                                    dipole_theory.sample_points(w.shape, rad.cells),
+                                    np.arange(*rad.window, dtype=np.float64), eps0, mu0, om)
+    keep = np.sin(rad.theta) > 0.5
+    ratio = smax[keep] / theory[keep]
     del lat
     torch.cuda.empty_cache()
-    return {"workload": f"radiation_{n}^3_{model}", "steps": w.steps, "sample_radius": round(float(rad.radius.mean()), 2),
-            "wavelength": round(rad.wavelength, 2), "samples": len(rad.cells), "run_s": round(wall, 4),
+    return {"model": model, "steps": w.steps, "run_s": round(wall, 4),
             "pattern_max_dev_from_sin2": round(float(np.abs(pattern - np.sin(rad.theta) ** 2).max()), 4),
-            "equatorial_flux_over_theory": [round(float(ratio.min()), 3), round(float(ratio.max()), 3)]}
+            "flux_over_continuum": {"mean": round(float(ratio.mean()), 4), "min": round(float(ratio.min()), 4),
+                                    "max": round(float(ratio.max()), 4)}}
 
 
 def time_precision(model: str, n: int, steps: int):
@@ -294,7 +332,11 @@ def time_precision(model: str, n: int, steps: int):
 
 
 def cpu_baseline(n: int, sample_steps: int):
-    """The FP64 oracle on the host cores: a few steps of the same 256^3 MM dipole lattice."""
+    """The FP64 oracle on the host cores: a few steps of the same 256^3 MM dipole
+    lattice with every OpenMP thread, and (in a child process with one thread)
+    a smaller sample of the same lattice single-threaded."""
+    import subprocess
+
     import oracle
     from paper_2309_08068_amd import inputs
 
@@ -305,8 +347,53 @@ def cpu_baseline(n: int, sample_steps: int):
     t0 = time.perf_counter()
     oracle.run(P, f, 0, sample_steps, probes=w.probes)
     dt = time.perf_counter() - t0
-    return {"value": w.n * sample_steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{sample_steps} steps of the {n}^3 MM dipole lattice, FP64, {dt:.1f} s"}
+    del f
+    one_steps = 2
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample", str(n), str(one_steps)],
+                         capture_output=True, text=True, env=env, timeout=600)
+    one = json.loads(res.stdout.strip().splitlines()[-1]) if res.returncode == 0 else None
+    return {"value": round(w.n * sample_steps / dt / 1e6, 2), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{sample_steps} steps of the {n}^3 MM dipole lattice, FP64, {dt:.1f} s",
+            "single_thread": None if one is None else {"value": round(one["mlups"], 3), "unit": "MLUPS", "cores": 1,
+                                                       "sample": f"{one_steps} steps of the same lattice, "
+                                                                 f"{one['seconds']:.1f} s"}}
+
+
+def oracle_sample(n: int, steps: int):
+    """Child process of cpu_baseline: time `steps` oracle steps, print JSON."""
+    import oracle
+    from paper_2309_08068_amd import inputs
+
+    w = inputs.dipole("mm", n=n, steps=steps)
+    P = oracle.Problem("mm", w.shape, sigma=w.sigma, currents=w.currents)
+    f = oracle.init(P, *w.fields0())
+    t0 = time.perf_counter()
+    oracle.run(P, f, 0, steps, probes=w.probes)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"mlups": w.n * steps / dt / 1e6, "seconds": dt, "threads": oracle.threads()}), flush=True)
+
+
+def stream_copy_gbs():
+    """A plain device copy of 1 GiB (torch copy_): read + write bytes over its
+    event-timed duration, the best of 5 launches."""
+    import torch
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best = 1e30
+    for _ in range(6):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * (1 << 30) / (best * 1e-3) / 1e9
 
 
 def main():
@@ -330,7 +417,12 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: only `steps` steps of the --only variants, then a plain "
                          "copy of 1 GiB (torch copy_) three times as the calibration kernel of known size")
+    ap.add_argument("--oracle-sample", nargs=2, type=int, metavar=("N", "STEPS"),
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_sample:
+        oracle_sample(*args.oracle_sample)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
               "not built", file=sys.stderr)
@@ -384,6 +476,8 @@ def main():
         print(f"# {model} {storage}: {r['mlups']:.0f} MLUPS, step kernel {r['kernel_ms']:.3f} ms, "
               f"{r['achieved_gbs']:.0f} GB/s ({100 * r['frac']:.1f}% of peak), tuning {r['tuning']}",
               file=sys.stderr, flush=True)
+    stream = stream_copy_gbs()
+    print(f"# torch copy of 1 GiB: {stream:.0f} GB/s", file=sys.stderr, flush=True)
     head = results.get("mm_f32") or next(iter(results.values()))
     traffic = head["traffic"]
     line = {
@@ -407,41 +501,66 @@ def main():
                      "traffic": None if traffic is None else round(traffic / 1e9 / (head["kernel_ms"] * 1e-3), 1),
                      "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": head["bytes_per_lu"] * head["cells"],
                      "kernel": f"row_step_kernel<{head['model'].upper()}, {head['storage']}>",
-                     "bytes_per_lu": head["bytes_per_lu"], "kernel_ms": round(head["kernel_ms"], 4)},
-        "variants": {k: {"mlups": round(v["mlups"], 1), "achieved_gbs": round(v["achieved_gbs"], 1),
-                         "frac": round(v["frac"], 4), "kernel_ms": round(v["kernel_ms"], 4),
-                         "bytes_per_lu": v["bytes_per_lu"], "tuning": v["tuning"],
-                         "traffic_gbs": None if v["traffic"] is None else round(v["traffic"] / 1e9 / (v["kernel_ms"] * 1e-3), 1)}
+                     "bytes_per_lu": head["bytes_per_lu"], "kernel_ms": round(head["kernel_ms"], 4),
+                     "stream_copy_gbs": round(stream, 1), "frac_of_stream_copy": round(head["achieved_gbs"] / stream, 4)},
+        # per variant: MLUPS, fraction of the HBM peak, step-kernel ms, measured traffic over algorithmic bytes
+        "variants": {k: {"mlups": round(v["mlups"], 1), "frac": round(v["frac"], 4), "kernel_ms": round(v["kernel_ms"], 4),
+                         "traffic_over_algorithmic": None if v["traffic"] is None else
+                         round(v["traffic"] / (v["bytes_per_lu"] * v["cells"]), 4)}
                      for k, v in results.items()},
         "adjoint_over_forward": None,
     }
     if not args.no_batch:
-        line["batched_1d"] = time_batch(args.batch_steps)
-        print(f"# batched 1-D: {line['batched_1d']}", file=sys.stderr, flush=True)
+        b = time_batch(args.batch_steps)
+        print(f"# batched 1-D: {b}", file=sys.stderr, flush=True)
+        line["batched_1d"] = {k: b[k] for k in ("workload", "launch", "steps_per_pass", "mlups",
+                                               "frac_of_one_step_roofline", "one_step_per_pass_mlups",
+                                               "one_step_per_pass_frac", "speedup_vs_per_instance")}
+        line["batched_1d"]["alu_frac"] = b["roofline_blocked"]["frac"]
     if not args.no_adjoint:
-        # HV is the model whose run stays bounded on this smooth 3-D medium.
         # keep = segments whose E frames the first forward holds: 1 is the
-        # minimal-memory schedule (every other segment recomputed), 10 holds
-        # 25 GB of frames, 30 holds all of them (75 GB, nothing recomputed).
-        # The headline ratio is the 10-segment schedule, sized for 288 GB parts.
-        runs = [time_adjoint("hv", args.adjoint_steps, 50, k) for k in (1, 10, 30)]
-        runs.append(time_adjoint("mm", args.adjoint_steps, 50, 1))
-        runs.append(time_adjoint("mmd", args.adjoint_steps, 50, 1))
-        line["adjoint"] = runs
-        line["adjoint_over_forward"] = runs[1]["ratio"]
-        for r in runs:
+        # minimal-memory schedule (every other segment recomputed); 10 holds
+        # 25 GB of frames for the 128 x 128 x 256 lattice, which 288 GB parts
+        # afford.  The MM gradients come from the 50-population adjoint and,
+        # at 24 / 50 of its traffic, from the difference form's adjoint; both
+        # are reported against the 50-population MM forward.
+        runs = []
+        for model, keep, fwd in (("hv", 1, None), ("hv", 10, None), ("mm", 1, None), ("mm", 10, None),
+                                 ("mmd", 10, "mm"), ("mmd", 10, None)):
+            r = time_adjoint(model, args.adjoint_steps, 50, keep, fwd)
             print(f"# adjoint: {r}", file=sys.stderr, flush=True)
+            runs.append(r)
+        line["adjoint"] = [{k: r[k] for k in ("model", "forward_model", "keep", "forward_s", "adjoint_total_s", "ratio",
+                                                "loss", "energy_max_over_initial", "growth_from_step", "check")}
+                           for r in runs]
+        pick = {(r["model"], r["forward_model"], r["keep"]): r["ratio"] for r in runs}
+        line["adjoint_over_forward"] = {"mm": pick[("mmd", "mm", 10)], "mm_50_populations": pick[("mm", "mm", 10)],
+                                        "hv": pick[("hv", "hv", 10)], "mmd": pick[("mmd", "mmd", 10)],
+                                        "workload": f"slab_128x128x256_{args.adjoint_steps}steps_K50_keep10"}
     if not args.no_radiation:
-        line["radiation_pattern"] = [radiation_pattern(m, args.n) for m in ("mm", "hv", "mmd")]
+        line["radiation_pattern"] = [radiation_pattern(m, args.n) for m in ("mm", "hv")]
         for r in line["radiation_pattern"]:
             print(f"# radiation: {r}", file=sys.stderr, flush=True)
     if not args.no_study:
         from paper_2309_08068_amd import study
-        line["refinement_study"] = study.study()
-        for r in line["refinement_study"]:
+        recs = study.study()
+        main_err = {"interface": "reflected", "skin": "rms", "dipole": "cost_B", "layers": "peak"}
+        summary = {}
+        for r in recs:
             print(f"# study: {r}", file=sys.stderr, flush=True)
+            e = summary.setdefault(r["experiment"], {"measure": main_err[r["experiment"]]})
+            m = e.setdefault(r["model"], {"size": [], "error": [], "gpu_ms": []})
+            m["size"].append(r["size"])
+            m["error"].append(float(f"{float(r[main_err[r['experiment']]]):.4g}"))
+            m["gpu_ms"].append(r["gpu_ms"])
+        line["refinement_study"] = summary
     if not args.no_sweep:
-        line["precision_sweep"] = [time_precision(m, args.sweep_n, args.sweep_steps) for m in ("mm", "hv")]
+        sweep = {}
+        for m in ("mm", "hv"):
+            res = time_precision(m, args.sweep_n, args.sweep_steps)
+            sweep[m] = {st: [v["frac"], v.get("rel_l2_vs_f32", [0.0, 0.0])[0]] for st, v in res["formats"].items()}
+        line["precision_sweep"] = {"workload": f"hertz_dipole_{args.sweep_n}^3_{args.sweep_steps}steps",
+                                   "fields": "storage: [fraction of HBM peak, rel L2 of E vs FP32 storage]", **sweep}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -123,7 +123,8 @@ def interface_errors(w, Ex: np.ndarray) -> Dict[str, float]:
 def skin_cost(w, amplitude: np.ndarray, z: np.ndarray) -> Dict[str, float]:
     """eq. (cost) over the conductor cells z (amplitude per cell, last period)
     where the theoretical amplitude is at least 1e-3 of A0 (the amplitude at
-    the conductor's face)."""
+    the conductor's face), and the root mean square of the per-cell relative
+    errors it sums."""
     model = w.model
     eps0, mu0 = inputs.VACUUM_CONSTANTS[model]
     omega = 2.0 * math.pi / w.meta["period"]
@@ -132,7 +133,10 @@ def skin_cost(w, amplitude: np.ndarray, z: np.ndarray) -> Dict[str, float]:
     A0 = amplitude[d == 0][0]
     theo = A0 * np.exp(-d / delta)
     keep = (d >= 0) & (theo >= 1e-3 * A0)
-    return {"cost": float(np.sum(((amplitude[keep] - theo[keep]) / theo[keep]) ** 2)), "skin_depth": delta}
+    rel2 = ((amplitude[keep] - theo[keep]) / theo[keep]) ** 2
+    # the cost is a sum over the cells, so it grows with their number; "rms"
+    # is the per-cell relative error, which shows the convergence directly
+    return {"cost": float(np.sum(rel2)), "rms": float(np.sqrt(np.mean(rel2))), "skin_depth": delta}
 
 
 def dipole_cost(w, E_amp: np.ndarray, B_amp: np.ndarray) -> Dict[str, float]:

@@ -63,3 +63,27 @@ def test_torch_reference_gradient_equals_finite_differences(model):
             Lm, _ = LOSS[model](am, sm, t["mu"], t["E0"], t["B0"], 6, 3)
             fd = (Lp - Lm).item() / (2 * h)
             assert abs(fd - g[k].item()) <= 1e-6 * max(1.0, abs(fd)), (which, k, fd, g[k].item())
+
+
+def test_stored_slab_finite_differences_are_converged():
+    """The stored central finite differences of the oracle's inverse-design
+    loss (tests/golden/slab_fd_32x32x128.json): taken again with half the
+    step on two cells they change by under 1e-5 relative, so their
+    truncation error (O(h^2)) is far below the 1e-3 the GPU adjoint is held
+    to; the 32 cells are distinct slab cells."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "slab_fd_32x32x128.json")
+    with open(path) as fh:
+        rec = json.load(fh)
+    nx, ny, nz = rec["shape"]
+    cells = rec["cells"]
+    assert len(set(cells)) == 32
+    assert all(rec["slab_z"][0] * nx * ny <= c < rec["slab_z"][1] * nx * ny for c in cells)
+    for model in ("mm", "hv"):
+        m = rec["models"][model]
+        assert len(m["eps"]) == len(m["sigma"]) == 32
+        for which in ("eps", "sigma"):
+            for full, half in zip(m[which], m[which + "_half_h"]):
+                assert abs(full - half) <= 1e-5 * abs(half), (model, which, full, half)
