@@ -57,7 +57,18 @@ def gpu_errors(w, ref64, cache, storage):
         far = away_from_source(w)
         cache[storage] = (rel(E, ref64[0]), rel(B, ref64[1]), elem(E[:, far], ref64[0][:, far]),
                           elem(B[:, far], ref64[1][:, far]), elem(E, ref64[0]), elem(B, ref64[1]))
+        print(f"{w.model} {storage} error of E by distance from the source: " + ", ".join(
+            f"r {lo}-{hi}: {rel(E[:, m], ref64[0][:, m]):.3e}" for (lo, hi), m in shells(w)), flush=True)
     return cache[storage]
+
+
+def shells(w, edges=(0, 4, 8, 16, 24)):
+    """Masks of the cells in shells of distance from the source (the sponge
+    starts 16 cells from the faces, 16 from the centre of the 64^3 box)."""
+    nx, ny, nz = w.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - nx // 2) ** 2 + (y - ny // 2) ** 2 + (z - nz // 2) ** 2).reshape(-1)
+    return [((lo, hi), (r >= lo) & (r < hi)) for lo, hi in zip(edges[:-1], edges[1:])]
 
 
 def away_from_source(w, r_min=4.0):
@@ -97,6 +108,9 @@ def test_shifted_storage_gain_with_gaussian_source(model):
     w = inputs.dipole(model, n=N64, steps=STEPS, source="gaussian")
     ref64 = oracle_fields(w, "f64")
     cache = {}
+    for st in ("f32", "bf16", "f16", "bf16_shifted", "f16_shifted"):
+        eE, eB = gpu_errors(w, ref64, cache, st)[:2]
+        print(f"{model} gaussian source {st}: relative L2 E {eE:.3e} B {eB:.3e}", flush=True)
     for shifted, plain in PLAIN.items():
         eE, eB = gpu_errors(w, ref64, cache, shifted)[:2]
         pE, pB = gpu_errors(w, ref64, cache, plain)[:2]
