@@ -122,8 +122,9 @@ size_t lbem_workspace_bytes(const lbem_desc *desc);
  * plane when they have more rows than one chunk holds (the last chunk
  * padded); other lattices store [Q][N].  A state is only meaningful to a
  * lattice with the same descriptor.
- * The padding is never read or written by the step kernels, so it costs no
- * traffic there, but it is real device memory: rows of nx cells take
+ * The step kernels use the padding only to finish a row's last 64-byte
+ * write piece (they store values there that nothing reads), so it costs
+ * almost no traffic, but it is real device memory: rows of nx cells take
  * 128, 256 or 512 cells (the next of these at or above nx), e.g. 288-cell rows
  * 512 (1.78x) and 384-cell rows 512 (1.33x: a 384^3 MM FP32 state is 15.1 GB
  * instead of 11.3 GB).  save_state / load_state copy the padded image, and
@@ -274,8 +275,9 @@ lbem_status lbem_check(lbem_lattice *lat, double max_energy, double *energy);
 lbem_status lbem_set_tuning(lbem_lattice *lat, const int32_t *form, const int32_t *blocks_per_cu);
 lbem_status lbem_get_tuning(lbem_lattice *lat, int32_t *form, int32_t *blocks_per_cu);
 
-/* Time every (form, cap) candidate for each parity over trial_steps launches
- * and keep the fastest.  backup: dev, lbem_state_size bytes; the state is
+/* Time every (form, cap) candidate for each parity over trial_steps launches,
+ * then the four fastest again over 2 trial_steps launches in two alternating
+ * rounds, and keep the fastest of those by their summed time.  backup: dev, lbem_state_size bytes; the state is
  * copied there first and restored afterwards, so the lattice is unchanged.
  * Synchronises the stream. */
 lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup);

@@ -247,6 +247,12 @@ __device__ __forceinline__ void lds_phase_barrier() {
     asm volatile("" ::: "memory");
 }
 
+// HBM writes whole 64-byte pieces: a store that covers only part of one
+// costs a read-modify-write of the piece.  A row whose byte length is not a
+// multiple of this ends in such a piece unless the padding cells after it
+// (never read as populations) are written too.
+constexpr uint32_t kWritePiece = 64;
+
 // Gather / scatter of the in-place AA streaming for a block that owns one
 // whole x-row of nx <= RB cells (y, z uniform; threads past the row idle).
 // Every HBM access is the aligned
@@ -263,17 +269,25 @@ struct RowIO {
     PopLayout L;
     uint32_t ny, x, xo, nx;
     bool live;  // x < nx: the row block has RB >= nx threads, those past the row idle
+    bool pad;   // an idle thread whose padding cell lies in the row's last kWritePiece bytes
     uint32_t yr[3], zr[3];
 
     // x: this thread's cell along the row (threadIdx.x unless a row is split
     // over several workgroups); the row length is L.nx <= RB.  An idle thread
-    // (x >= nx) loads the row's last cell, which keeps every load outside a
-    // branch, and stores nothing; in LDS it only writes slot RB - 1 >= nx,
+    // (x >= nx) computes on a copy of some cell's data and stores nothing of
+    // it, except that the idle threads whose own cell is a padding cell in
+    // the row's last write piece (below RB <= pitch) store their values there
+    // and load from there, so that a row's stores cover whole pieces.  The
+    // other idle threads load the row's last cell, which keeps every load
+    // outside a branch.  In LDS an idle thread only writes slot RB - 1 >= nx,
     // which no live thread reads (idle threads only exist when nx < RB).
     __device__ RowIO(const void *p, const PopLayout &l, uint32_t ny_, uint32_t nz, uint32_t row,
                      uint32_t x_ = threadIdx.x)
-        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_ < l.nx ? x_ : l.nx - 1u),
-          xo((x_ < l.nx ? x_ : l.nx - 1u) * uint32_t(sizeof(T))), nx(l.nx), live(x_ < l.nx) {
+        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_ < l.nx ? x_ : l.nx - 1u), nx(l.nx),
+          live(x_ < l.nx),
+          pad(x_ >= l.nx &&
+              x_ * uint32_t(sizeof(T)) < (l.nx * uint32_t(sizeof(T)) + kWritePiece - 1u) / kWritePiece * kWritePiece) {
+        xo = (live || pad ? x_ : l.nx - 1u) * uint32_t(sizeof(T));
         const uint32_t y = row % ny_, z = row / ny_;
         yr[0] = y == 0 ? ny_ - 1 : y - 1;
         yr[1] = y;
@@ -293,6 +307,7 @@ struct RowIO {
     __device__ uint64_t row_base(int q, int dy, int dz) const {
         return (L.base(row_of(dy, dz)) + uint64_t(q) * L.C) * sizeof(T);
     }
+    // the thread's own cell (a padding cell for a `pad` thread)
     __device__ T *at(int q, int dy, int dz) const {
         return reinterpret_cast<T *>(const_cast<char *>(pop) + row_base(q, dy, dz) + xo);
     }
@@ -330,8 +345,9 @@ struct RowIO {
 
     template <int ODD>
     __device__ void scatter(const float (&f)[M::Q], T (*sh)[RB], float scale) const {
+        const bool st = live || pad;
         if (!ODD) {
-            if (live) {
+            if (st) {
 #pragma unroll
                 for (int q = 0; q < M::Q; ++q) put<T, true>(at(M::opp(q), 0, 0), ST::pack(f[q], scale));
             }
@@ -341,13 +357,13 @@ struct RowIO {
 #pragma unroll
             for (int q = 0; q < M::Q; ++q) {
                 if (M::vel(q, 0) == 0) {
-                    if (live) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
+                    if (st) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
                 } else {
                     sh[k++][slot(M::vel(q, 0))] = ST::pack(f[q], scale);
                 }
             }
             lds_phase_barrier();
-            if (live) {
+            if (st) {
                 k = 0;
 #pragma unroll
                 for (int q = 0; q < M::Q; ++q)
@@ -371,12 +387,17 @@ struct RowIO {
 
     template <int ODD>
     __device__ void scatter_direct(const float (&f)[M::Q], float scale) const {
-        if (!live) return;
+        if (live) {
 #pragma unroll
-        for (int q = 0; q < M::Q; ++q) {
-            if (!ODD) put<T, true>(at(M::opp(q), 0, 0), ST::pack(f[q], scale));
-            else if (M::vel(q, 0) == 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
-            else put<T, false>(at_x(q, M::vel(q, 1), M::vel(q, 2), M::vel(q, 0)), ST::pack(f[q], scale));
+            for (int q = 0; q < M::Q; ++q) {
+                if (!ODD) put<T, true>(at(M::opp(q), 0, 0), ST::pack(f[q], scale));
+                else if (M::vel(q, 0) == 0) put<T, true>(at(q, M::vel(q, 1), M::vel(q, 2)), ST::pack(f[q], scale));
+                else put<T, false>(at_x(q, M::vel(q, 1), M::vel(q, 2), M::vel(q, 0)), ST::pack(f[q], scale));
+            }
+        } else if (pad) {  // own padding cell, every population
+#pragma unroll
+            for (int q = 0; q < M::Q; ++q)
+                put<T, false>(at(q, ODD ? M::vel(q, 1) : 0, ODD ? M::vel(q, 2) : 0), ST::pack(f[q], scale));
         }
     }
 };

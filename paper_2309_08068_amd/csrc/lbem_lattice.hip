@@ -1147,48 +1147,63 @@ lbem_status lbem_autotune(lbem_lattice *lat, int32_t trial_steps, void *backup) 
     st = hip_check(hipEventCreate(&e0), "event");
     if (!st) st = hip_check(hipEventCreate(&e1), "event");
     static const int caps[] = {0, 2, 3, 4};
-    int32_t best_form[2] = {lat->tune_form[0], lat->tune_form[1]};
-    int32_t best_cap[2] = {lat->tune_cap[0], lat->tune_cap[1]};
     // every candidate times one parity's kernel alone; the data it leaves is
     // not a valid state, which is why the state is restored afterwards
     const StepArgs a = base_step_args(lat);
+    struct Cand {
+        int32_t form, cap;
+        float ms;
+    };
+    // milliseconds of `launches` launches of one parity under (form, cap)
+    auto time_cand = [&](int p, const Cand &c, int launches, float &ms) {
+        int32_t f2[2] = {lat->tune_form[0], lat->tune_form[1]}, c2[2] = {lat->tune_cap[0], lat->tune_cap[1]};
+        f2[p] = c.form;
+        c2[p] = c.cap;
+        lbem_status s2 = lbem_set_tuning(lat, f2, c2);
+        if (s2) return s2;
+        dispatch_step(lat, a, p);  // warm-up
+        s2 = hip_check(hipEventRecord(e0, lat->stream), "record");
+        for (int k = 0; k < launches && !s2; ++k) dispatch_step(lat, a, p);
+        if (!s2) s2 = hip_check(hipGetLastError(), "trial launch");
+        if (!s2) s2 = hip_check(hipEventRecord(e1, lat->stream), "record");
+        if (!s2) s2 = hip_check(hipEventSynchronize(e1), "sync");
+        if (!s2) s2 = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        return s2;
+    };
     for (int p = 0; p < 2 && !st; ++p) {
-        float best = 1e30f;
         // candidate forms: kernels 0-2 (row lattices), 3 (rows longer than a
         // split workgroup), each in both block orders; generic lattices: order only
         const uint32_t rb = row_block(&lat->d);
-        int forms[8], nforms = 0;
+        std::vector<Cand> cands;
         for (int order = 0; order < 2; ++order)
             for (int k = 0; k < 4; ++k)
-                if ((rb && (k < 3 || rb > uint32_t(kSegThreads))) || (!rb && k == 0)) forms[nforms++] = k + 4 * order;
-        for (int fi = 0; fi < nforms && !st; ++fi)
-            for (int cap : caps) {
-                const int form = forms[fi];
-                int32_t f2[2] = {lat->tune_form[0], lat->tune_form[1]}, c2[2] = {lat->tune_cap[0], lat->tune_cap[1]};
-                f2[p] = form;
-                c2[p] = cap;
-                st = lbem_set_tuning(lat, f2, c2);
-                if (st) break;
-                dispatch_step(lat, a, p);  // warm-up
-                st = hip_check(hipEventRecord(e0, lat->stream), "record");
-                for (int k = 0; k < trial_steps && !st; ++k) dispatch_step(lat, a, p);
-                if (!st) st = hip_check(hipGetLastError(), "trial launch");
-                if (!st) st = hip_check(hipEventRecord(e1, lat->stream), "record");
-                if (!st) st = hip_check(hipEventSynchronize(e1), "sync");
-                float ms = 0.f;
-                if (!st) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-                if (!st && ms < best) {
-                    best = ms;
-                    best_form[p] = form;
-                    best_cap[p] = cap;
-                }
-            }
-        if (!st) {
-            int32_t f2[2] = {lat->tune_form[0], lat->tune_form[1]}, c2[2] = {lat->tune_cap[0], lat->tune_cap[1]};
-            f2[p] = best_form[p];
-            c2[p] = best_cap[p];
-            st = lbem_set_tuning(lat, f2, c2);
+                if ((rb && (k < 3 || rb > uint32_t(kSegThreads))) || (!rb && k == 0))
+                    for (int cap : caps) cands.push_back({k + 4 * order, cap, 0.f});
+        // stage 1: every candidate over trial_steps launches
+        for (Cand &c : cands) {
+            st = time_cand(p, c, trial_steps, c.ms);
+            if (st) break;
         }
+        if (st) break;
+        // stage 2: the fastest few again, over twice as many launches in
+        // alternating rounds, so that one noisy stage-1 timing does not decide
+        std::stable_sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
+        const size_t nf = std::min<size_t>(4, cands.size());
+        for (size_t i = 0; i < nf; ++i) cands[i].ms = 0.f;
+        for (int round = 0; round < 2 && !st; ++round)
+            for (size_t i = 0; i < nf && !st; ++i) {
+                float ms = 0.f;
+                st = time_cand(p, cands[i], 2 * trial_steps, ms);
+                cands[i].ms += ms;
+            }
+        if (st) break;
+        size_t best = 0;
+        for (size_t i = 1; i < nf; ++i)
+            if (cands[i].ms < cands[best].ms) best = i;
+        int32_t f2[2] = {lat->tune_form[0], lat->tune_form[1]}, c2[2] = {lat->tune_cap[0], lat->tune_cap[1]};
+        f2[p] = cands[best].form;
+        c2[p] = cands[best].cap;
+        st = lbem_set_tuning(lat, f2, c2);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
