@@ -258,7 +258,7 @@ lbem_status lbem_check(lbem_lattice *lat, double max_energy, double *energy);
 /* Launch tuning of the step kernel, per parity (index 0 even, 1 odd time
  * level).  form[p] = kernel + 4 * order:
  *   kernel, for lattices whose x extent nx is 128, 256, 384 or 512, or
- *     fills at least 3/4 of the next of 256, 384, 512 (one workgroup of that
+ *     fills at least 3/4 of the next of 128, 256, 384, 512 (one workgroup of that
  *     many threads per x-row, those past nx idle): 0 and 1 are the row
  *     form, whose +-1 x shifts go
  *     through LDS so that every HBM access is an aligned row, with store

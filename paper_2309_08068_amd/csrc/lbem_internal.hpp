@@ -23,16 +23,17 @@ struct WsLayout {
 WsLayout layout(const lbem_desc *d);
 
 // Threads per block of the row form of the step kernel (one block per x-row):
-// nx itself for 128, 256, 384, 512, else the next of 256, 384, 512 when the
-// row fills at least 3/4 of it (threads past nx idle); 0 when the lattice uses
-// the generic form.  Measured on MI355X: rows that fill 3/4 of their block
-// gain 8-18 points of the HBM peak over the generic form (192, 250, 300, 320,
-// 500 cells); emptier ones (100 cells in 128 threads) lose.
+// nx itself for 128, 256, 384, 512, else the next of 128, 256, 384, 512 when
+// the row fills at least 3/4 of it (threads past nx idle); 0 when the lattice
+// uses the generic form.  Measured on MI355X: rows that fill 3/4 of their
+// block gain 2-18 points of the HBM peak over the generic form (100, 120, 192,
+// 250, 300, 320, 500 cells), once their stores finish the row's last write
+// piece (see RowIO).
 inline uint32_t row_block(const lbem_desc *d) {
     const uint32_t nx = uint32_t(d->nx);
     if (nx == 128 || nx == 256 || nx == 384 || nx == 512) return nx;
-    if (nx <= 128 || nx > 512) return 0u;
-    const uint32_t rb = nx <= 256 ? 256u : nx <= 384 ? 384u : 512u;
+    if (nx < 96 || nx > 512) return 0u;
+    const uint32_t rb = nx <= 128 ? 128u : nx <= 256 ? 256u : nx <= 384 ? 384u : 512u;
     return 4 * nx >= 3 * rb ? rb : 0u;
 }
 

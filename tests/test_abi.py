@@ -104,11 +104,12 @@ def test_shifted_storage_sizes(lib, storage, q):
 @pytest.mark.parametrize("shape,storage,chunks,chunk_cells", [
     ((256, 20, 13), "f32", 9, 8192), ((384, 10, 13), "f32", 9, 8192), ((512, 3, 45), "f32", 9, 8192),
     ((128, 9, 60), "f32", 9, 8192), ((256, 16, 16), "f32", 8, 8192), ((256, 20, 13), "bf16", 5, 16384),
-    ((128, 8, 8), "f32", 1, 0), ((100, 30, 40), "f32", 1, 0), ((200, 9, 41), "f32", 12, 8192),
+    ((128, 8, 8), "f32", 1, 0), ((90, 30, 40), "f32", 1, 0), ((100, 30, 40), "f32", 19, 8192),
+    ((120, 9, 70), "bf16", 5, 16384), ((200, 9, 41), "f32", 12, 8192),
     ((200, 9, 41), "bf16", 6, 16384), ((60, 30, 40), "f32", 1, 0), ((600, 10, 10), "f32", 1, 0)])
 def test_population_layout_chunks(lib, shape, storage, chunks, chunk_cells):
     """Row-form lattices (nx = 128, 256, 384, 512, or a row filling 3/4 of
-    the next of 256, 384, 512 threads) store populations in chunks of a
+    the next of 128, 256, 384, 512 threads) store populations in chunks of a
     power of two of x-rows with at most 32 KB per population plane, the rows
     a power of two of cells apart; the last chunk is padded.  A lattice
     that fits in one chunk (rows still padded), and any generic-form lattice,

@@ -83,16 +83,17 @@ def run_oracle(model, shape, p, steps, real="f64", probes=None, det_z=None, ener
 
 
 # generic form (odd sizes, ragged last block, axes of length 1) and the row form
-# (x extent 65..512: one block of 128, 256, 384 or 512 threads per x-row, LDS
+# (x extent 96..512: one block of 128, 256, 384 or 512 threads per x-row, LDS
 # x-shifts), in one layout chunk and -- (128, 9, 60) .. (512, 3, 45), with
 # more x-rows than a chunk holds -- across chunks with a partial last chunk;
-# of the last five, (100, 7, 9) takes the generic form and the others have
-# rows shorter than their block (idle threads past nx), (200, 9, 41) also
+# of the last seven, (90, 7, 9) takes the generic form and the others have
+# rows shorter than their block (idle threads past nx, some of which finish
+# the row's last 64-byte write piece), (120, 9, 70) and (200, 9, 41) also
 # across chunks; every row-form lattice has rows a power of two of cells apart
 SHAPES = [(1, 1, 17), (7, 5, 9), (16, 16, 16), (33, 3, 5), (300, 1, 1), (1, 40, 1), (9, 1, 31),
           (128, 3, 5), (256, 2, 3), (384, 1, 2), (512, 2, 1),
           (128, 9, 60), (256, 20, 13), (384, 10, 13), (512, 3, 45),
-          (100, 7, 9), (193, 3, 5), (200, 9, 41), (300, 4, 7), (450, 3, 13)]
+          (90, 7, 9), (100, 7, 9), (120, 9, 70), (193, 3, 5), (200, 9, 41), (300, 4, 7), (450, 3, 13)]
 
 
 @pytest.mark.parametrize("model", MODELS)
