@@ -265,7 +265,10 @@ constexpr uint32_t kWritePiece = 64;
 template <class M, class ST, int RB>
 struct RowIO {
     using T = typename ST::T;
-    const char *pop;
+    // global address space kept explicit: a generic pointer that has passed
+    // through late() would otherwise turn every access into a flat one
+    using gchar = __attribute__((address_space(1))) char;
+    gchar *pop;
     PopLayout L;
     uint32_t ny, x, xo, nx;
     bool live;  // x < nx: the row block has RB >= nx threads, those past the row idle
@@ -283,7 +286,7 @@ struct RowIO {
     // which no live thread reads (idle threads only exist when nx < RB).
     __device__ RowIO(const void *p, const PopLayout &l, uint32_t ny_, uint32_t nz, uint32_t row,
                      uint32_t x_ = threadIdx.x)
-        : pop(static_cast<const char *>(p)), L(l), ny(ny_), x(x_ < l.nx ? x_ : l.nx - 1u), nx(l.nx),
+        : pop((gchar *)(p)), L(l), ny(ny_), x(x_ < l.nx ? x_ : l.nx - 1u), nx(l.nx),
           live(x_ < l.nx),
           pad(x_ >= l.nx &&
               x_ * uint32_t(sizeof(T)) < (l.nx * uint32_t(sizeof(T)) + kWritePiece - 1u) / kWritePiece * kWritePiece) {
@@ -309,10 +312,10 @@ struct RowIO {
     }
     // the thread's own cell (a padding cell for a `pad` thread)
     __device__ T *at(int q, int dy, int dz) const {
-        return reinterpret_cast<T *>(const_cast<char *>(pop) + row_base(q, dy, dz) + xo);
+        return (T *)(pop + row_base(q, dy, dz) + xo);
     }
     __device__ T *at_x(int q, int dy, int dz, int dx) const {
-        return reinterpret_cast<T *>(const_cast<char *>(pop) + row_base(q, dy, dz) + xw(dx) * uint32_t(sizeof(T)));
+        return (T *)(pop + row_base(q, dy, dz) + xw(dx) * uint32_t(sizeof(T)));
     }
     // store addresses formed after the collision (see late_addresses)
     __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo), "+v"(x) : "v"(after)); }
