@@ -322,8 +322,13 @@ struct RowIO {
     // cell index of x + (dx, dy, dz), |d| <= 1, periodic (for per-cell arrays)
     __device__ uint32_t cell(int dx, int dy, int dz) const { return row_of(dy, dz) * nx + xw(dx); }
 
-    template <int ODD>
-    __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale) const {
+    // read_phase(f) runs on the complete populations inside the odd gather's
+    // LDS read phase (between its barriers), where it may read other LDS arrays
+    struct NoHook {
+        __device__ void operator()(float (&)[M::Q]) const {}
+    };
+    template <int ODD, class Hook = NoHook>
+    __device__ void gather(float (&f)[M::Q], T (*sh)[RB], float inv_scale, Hook &&read_phase = Hook()) const {
         if (!ODD) {
 #pragma unroll
             for (int q = 0; q < M::Q; ++q) f[q] = ST::cvt(raw<T, true>(at(q, 0, 0)), inv_scale);
@@ -342,6 +347,7 @@ struct RowIO {
 #pragma unroll
             for (int q = 0; q < M::Q; ++q)
                 if (M::vel(q, 0) != 0) f[q] = ST::cvt(sh[k++][slot(-M::vel(q, 0))], inv_scale);
+            read_phase(f);
             lds_phase_barrier();
         }
     }
@@ -401,6 +407,115 @@ struct RowIO {
 #pragma unroll
             for (int q = 0; q < M::Q; ++q)
                 put<T, false>(at(q, ODD ? M::vel(q, 1) : 0, ODD ? M::vel(q, 2) : 0), ST::pack(f[q], scale));
+        }
+    }
+};
+
+// ------------------------------------------------------------ record exchange
+// Shifted storage in the row form (a block's threads on one x-row, RowIO).
+// Population q arriving at x adds back phi_q of the record at x - v_q.  The
+// two velocities with the same (v_y, v_z) and opposite x components read one
+// neighbour row at x - 1 and x + 1.  Instead of two shifted record loads per
+// cell, each thread loads that row's record at its own x (aligned), evaluates
+// phi for the reader at x + 1 and for the reader at x - 1, and passes both
+// through LDS (xs).  Velocities without an x component load their record at x
+// directly.  The values are the ones unshift() adds, bit for bit.
+template <class M>
+constexpr int n_xvel() {
+    int n = 0;
+    for (int k = 0; k < Shift<M>::kNV; ++k) n += Shift<M>::vel(k, 0) != 0;
+    return n;
+}
+// rank of velocity k among those with (xv = true) or without an x component
+template <class M>
+constexpr int vel_rank(int k, bool xv) {
+    int n = 0;
+    for (int j = 0; j < k; ++j) n += (Shift<M>::vel(j, 0) != 0) == xv;
+    return n;
+}
+// the velocity with the opposite x component and the same (v_y, v_z)
+template <class M>
+constexpr int xvel_partner(int k) {
+    for (int j = 0; j < Shift<M>::kNV; ++j)
+        if (Shift<M>::vel(j, 0) == -Shift<M>::vel(k, 0) && Shift<M>::vel(j, 1) == Shift<M>::vel(k, 1) &&
+            Shift<M>::vel(j, 2) == Shift<M>::vel(k, 2))
+            return j;
+    return -1;
+}
+template <class M>
+constexpr bool xvel_paired() {
+    for (int k = 0; k < Shift<M>::kNV; ++k)
+        if (Shift<M>::vel(k, 0) != 0 && xvel_partner<M>(k) < 0) return false;
+    return true;
+}
+static_assert(xvel_paired<MM>() && xvel_paired<MMD>() && xvel_paired<HV>(), "x velocities come in opposite pairs");
+
+template <class M, int RB>
+struct RecX {
+    using S = Shift<M>;
+    static constexpr int kX = n_xvel<M>(), kN = S::kNV - kX, P = S::kNPhi;
+    // The velocities without an x component keep, from the record load until
+    // the populations are gathered, either their phi values (P <= 4) or the
+    // packed record (4 words, fewer registers when P > 4).
+    static constexpr bool kHoldPhi = P <= 4;
+    static constexpr int kHeld = kHoldPhi ? P : 4;
+    // xs: LDS float[kX * P][RB]; un: the held values
+    template <int K = 0, class IO>
+    __device__ static void publish(const IO &io, const u32x4 *__restrict__ rec, float (*xs)[RB],
+                                   float (&un)[kN][kHeld]) {
+        if constexpr (K < S::kNV) {
+            constexpr int vx = S::vel(K, 0), vy = S::vel(K, 1), vz = S::vel(K, 2);
+            if constexpr (vx == 0) {
+                const u32x4 w = rec[io.cell(0, -vy, -vz)];
+                float(&h)[kHeld] = un[vel_rank<M>(K, false)];
+                if constexpr (kHoldPhi) {
+                    S::template phi<K>(rec_unpack(w), 1.f, h);
+                } else {
+                    h[0] = __uint_as_float(w.x);
+                    h[1] = __uint_as_float(w.y);
+                    h[2] = __uint_as_float(w.z);
+                    h[3] = __uint_as_float(w.w);
+                }
+            } else if constexpr (vx > 0) {
+                constexpr int K2 = xvel_partner<M>(K);
+                const Rec r = rec_unpack(rec[io.cell(0, -vy, -vz)]);
+                float up[P], um[P];
+                S::template phi<K>(r, 1.f, up);   // for the reader at x + 1
+                S::template phi<K2>(r, 1.f, um);  // for the reader at x - 1
+                const uint32_t sp = io.slot(1), sm = io.slot(-1);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    xs[vel_rank<M>(K, true) * P + j][sp] = up[j];
+                    xs[vel_rank<M>(K2, true) * P + j][sm] = um[j];
+                }
+            }
+            publish<K + 1>(io, rec, xs, un);
+        }
+    }
+    // after a barrier: add every velocity's phi to the gathered populations
+    template <int K = 0, class IO>
+    __device__ static void collect(const IO &io, const float (*xs)[RB], const float (&un)[kN][kHeld],
+                                   float (&f)[M::Q]) {
+        if constexpr (K < S::kNV) {
+            if constexpr (S::vel(K, 0) == 0) {
+                const float(&h)[kHeld] = un[vel_rank<M>(K, false)];
+                if constexpr (kHoldPhi) {
+                    S::template apply<K>(f, h);
+                } else {
+                    const u32x4 w = {__float_as_uint(h[0]), __float_as_uint(h[1]), __float_as_uint(h[2]),
+                                     __float_as_uint(h[3])};
+                    float u[P];
+                    S::template phi<K>(rec_unpack(w), 1.f, u);
+                    S::template apply<K>(f, u);
+                }
+            } else {
+                const uint32_t own = io.slot(0);
+                float u[P];
+#pragma unroll
+                for (int j = 0; j < P; ++j) u[j] = xs[vel_rank<M>(K, true) * P + j][own];
+                S::template apply<K>(f, u);
+            }
+            collect<K + 1>(io, xs, un, f);
         }
     }
 };

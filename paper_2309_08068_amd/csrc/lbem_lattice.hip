@@ -133,10 +133,26 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
     const uint32_t c = row * a.nx + (live ? x : 0u);
     const size_t N = a.N;
     RowIO<M, ST, RB> io(a.pop, a.pl, a.ny, a.nz, row, x);
+    // shifted storage: the LDS forms exchange the x-shifted records (RecX)
+    constexpr bool XREC = ST::kShift && !DIRECT;
+    using RX = RecX<M, RB>;
+    __shared__ float xs[XREC ? RX::kX * RX::P : 1][XREC ? RB : 1];
+    float un[XREC ? RX::kN : 1][RX::kHeld];
+    if constexpr (XREC) RX::publish(io, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]), xs, un);
     float f[M::Q];
-    if (DIRECT) io.template gather_direct<ODD>(f, a.inv_scale);
-    else io.template gather<ODD>(f, sh, a.inv_scale);
-    if constexpr (ST::kShift) {
+    if (DIRECT) {
+        io.template gather_direct<ODD>(f, a.inv_scale);
+    } else if constexpr (XREC && ODD) {
+        // the gather's first barrier orders the xs writes; read them in its read phase
+        io.template gather<ODD>(f, sh, a.inv_scale, [&](float (&g)[M::Q]) { RX::collect(io, xs, un, g); });
+    } else {
+        io.template gather<ODD>(f, sh, a.inv_scale);
+        if constexpr (XREC) {
+            lds_phase_barrier();
+            RX::collect(io, xs, un, f);
+        }
+    }
+    if constexpr (ST::kShift && !XREC) {
         if (live)
             unshift<M>(f, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]),
                        [&](int dx, int dy, int dz) { return io.cell(dx, dy, dz); });

@@ -461,15 +461,20 @@ __device__ __forceinline__ u32x4 rec_pack(const float E[3], const float B[3], fl
 }
 
 // Per model: the distinct moving velocities k (every shifted population
-// belongs to exactly one) and f[q] += s * phi_q(R) over the populations of k.
+// belongs to exactly one), phi<k>(R, s, u): the kNPhi distinct values of
+// s * phi_q(R) over the populations q of k, and apply<k>(f, u): f_q += those
+// values.  The products and sums are written out with explicit FMAs, so that
+// a value computed by one thread and handed to another (see the row form's
+// record exchange) has the same bits as one computed and applied in place.
 template <class M>
 struct Shift;
 template <>
 struct Shift<MM> {
-    static constexpr int kNV = 12;  // k = p * 4 + i; populations 2k, 2k+1, 24+2k, 24+2k+1
+    static constexpr int kNV = 12;    // k = p * 4 + i; populations 2k, 2k+1, 24+2k, 24+2k+1
+    static constexpr int kNPhi = 2;   // +-u0 (electric pair), +-u1 (magnetic pair)
     __host__ __device__ static constexpr int vel(int k, int a) { return kMMV[k / 4][k % 4][a]; }
     template <int K>
-    __device__ static void add(float (&f)[50], const Rec &r, float s) {
+    __device__ static void phi(const Rec &r, float s, float (&u)[kNPhi]) {
         constexpr int p = K / 4, i = K % 4;
         float ee = 0.f, bb = 0.f;
 #pragma unroll
@@ -478,20 +483,24 @@ struct Shift<MM> {
             if (kMMB[p][a] != 0) bb += kMMB[p][a] > 0 ? r.B[a] : -r.B[a];
         }
         // E.e_{i0} = ee / 2; f0_eq = eps/4 E.e + B.b/(8 mu), f1_eq = E.e/4 + B.b/8
-        const float u0 = s * (0.125f * r.eps * ee + 0.125f * r.imu * bb);
-        const float u1 = s * (0.125f * ee + 0.125f * bb);
-        f[2 * K] += u0;
-        f[2 * K + 1] -= u0;
-        f[24 + 2 * K] += u1;
-        f[24 + 2 * K + 1] -= u1;
+        u[0] = s * __builtin_fmaf(0.125f * r.eps, ee, (0.125f * r.imu) * bb);
+        u[1] = s * (0.125f * ee + 0.125f * bb);  // both products exact
+    }
+    template <int K>
+    __device__ static void apply(float (&f)[50], const float (&u)[kNPhi]) {
+        f[2 * K] += u[0];
+        f[2 * K + 1] -= u[0];
+        f[24 + 2 * K] += u[1];
+        f[24 + 2 * K + 1] -= u[1];
     }
 };
 template <>
 struct Shift<MMD> {
     static constexpr int kNV = 12;  // k = p * 4 + i; populations k, 12 + k
+    static constexpr int kNPhi = 2;
     __host__ __device__ static constexpr int vel(int k, int a) { return kMMV[k / 4][k % 4][a]; }
     template <int K>
-    __device__ static void add(float (&f)[24], const Rec &r, float s) {
+    __device__ static void phi(const Rec &r, float s, float (&u)[kNPhi]) {
         constexpr int p = K / 4, i = K % 4;
         float ee = 0.f, bb = 0.f;
 #pragma unroll
@@ -500,21 +509,37 @@ struct Shift<MMD> {
             if (kMMB[p][a] != 0) bb += kMMB[p][a] > 0 ? r.B[a] : -r.B[a];
         }
         // d = 2 u (see Shift<MM>)
-        f[K] += s * (0.25f * r.eps * ee + 0.25f * r.imu * bb);
-        f[12 + K] += s * (0.25f * ee + 0.25f * bb);
+        u[0] = s * __builtin_fmaf(0.25f * r.eps, ee, (0.25f * r.imu) * bb);
+        u[1] = s * (0.25f * ee + 0.25f * bb);
+    }
+    template <int K>
+    __device__ static void apply(float (&f)[24], const float (&u)[kNPhi]) {
+        f[K] += u[0];
+        f[12 + K] += u[1];
     }
 };
 template <>
 struct Shift<HV> {
-    static constexpr int kNV = 6;  // k = i; populations 3i + a, 18 + 3i + a
+    static constexpr int kNV = 6;    // k = i; populations 3i + a, 18 + 3i + a
+    static constexpr int kNPhi = 6;  // e_a, h_a
     __host__ __device__ static constexpr int vel(int k, int a) { return kHVV[k][a]; }
     template <int K>
-    __device__ static void add(float (&f)[36], const Rec &r, float s) {
-        // e_eq = (3 eps_r E - v x B / mu_r) / 6,  h_eq = (B + 3 v x E) / 6
+    __device__ static void phi(const Rec &r, float s, float (&u)[kNPhi]) {
+        // e_eq = (3 eps_r E - v x B / mu_r) / 6,  h_eq = (B + 3 v x E) / 6; the
+        // cross products of an axis velocity are single signed terms (exact)
+        const float ke = 0.5f * r.eps, km = (1.f / 6.f) * r.imu;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            f[3 * K + a] += s * (0.5f * r.eps * r.E[a] - (1.f / 6.f) * r.imu * hv_vcross<K>(r.B, a));
-            f[18 + 3 * K + a] += s * ((1.f / 6.f) * r.B[a] + 0.5f * hv_vcross<K>(r.E, a));
+            u[a] = s * __builtin_fmaf(ke, r.E[a], -(km * hv_vcross<K>(r.B, a)));
+            u[3 + a] = s * __builtin_fmaf(0.5f, hv_vcross<K>(r.E, a), (1.f / 6.f) * r.B[a]);
+        }
+    }
+    template <int K>
+    __device__ static void apply(float (&f)[36], const float (&u)[kNPhi]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            f[3 * K + a] += u[a];
+            f[18 + 3 * K + a] += u[3 + a];
         }
     }
 };
@@ -523,8 +548,9 @@ struct Shift<HV> {
 template <class M, int K = 0, class F>
 __device__ __forceinline__ void shift_all(float (&f)[M::Q], float s, F &&rec_of) {
     if constexpr (K < Shift<M>::kNV) {
-        const Rec r = rec_of(K);
-        Shift<M>::template add<K>(f, r, s);
+        float u[Shift<M>::kNPhi];
+        Shift<M>::template phi<K>(rec_of(K), s, u);
+        Shift<M>::template apply<K>(f, u);
         shift_all<M, K + 1>(f, s, rec_of);
     }
 }
