@@ -318,7 +318,9 @@ struct RowIO {
         return (T *)(pop + row_base(q, dy, dz) + xw(dx) * uint32_t(sizeof(T)));
     }
     // store addresses formed after the collision (see late_addresses)
-    __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo), "+v"(x) : "v"(after)); }
+    // (the plane stride too: otherwise the compiler keeps every plane's offset
+    // from the loads live in scalar registers, and spills them, until the stores)
+    __device__ void late(float after) { asm volatile("" : "+s"(pop), "+v"(xo), "+v"(x), "+s"(L.C) : "v"(after)); }
     // cell index of x + (dx, dy, dz), |d| <= 1, periodic (for per-cell arrays)
     __device__ uint32_t cell(int dx, int dy, int dz) const { return row_of(dy, dz) * nx + xw(dx); }
 
@@ -454,28 +456,19 @@ template <class M, int RB>
 struct RecX {
     using S = Shift<M>;
     static constexpr int kX = n_xvel<M>(), kN = S::kNV - kX, P = S::kNPhi;
-    // The velocities without an x component keep, from the record load until
-    // the populations are gathered, either their phi values (P <= 4) or the
-    // packed record (4 words, fewer registers when P > 4).
-    static constexpr bool kHoldPhi = P <= 4;
-    static constexpr int kHeld = kHoldPhi ? P : 4;
-    // xs: LDS float[kX * P][RB]; un: the held values
+    // Worth it where most velocities have an x component (MM and the
+    // difference form: 8 of 12).  HV (2 of 6, six phi values per velocity)
+    // saves one record load of six and measured slower with the exchange.
+    static constexpr bool kUse = 2 * kX >= S::kNV;
+    // xs: LDS float[kX * P][RB]; un: phi of the velocities without an x
+    // component, held from the record load until the populations are gathered
     template <int K = 0, class IO>
     __device__ static void publish(const IO &io, const u32x4 *__restrict__ rec, float (*xs)[RB],
-                                   float (&un)[kN][kHeld]) {
+                                   float (&un)[kN][P]) {
         if constexpr (K < S::kNV) {
             constexpr int vx = S::vel(K, 0), vy = S::vel(K, 1), vz = S::vel(K, 2);
             if constexpr (vx == 0) {
-                const u32x4 w = rec[io.cell(0, -vy, -vz)];
-                float(&h)[kHeld] = un[vel_rank<M>(K, false)];
-                if constexpr (kHoldPhi) {
-                    S::template phi<K>(rec_unpack(w), 1.f, h);
-                } else {
-                    h[0] = __uint_as_float(w.x);
-                    h[1] = __uint_as_float(w.y);
-                    h[2] = __uint_as_float(w.z);
-                    h[3] = __uint_as_float(w.w);
-                }
+                S::template phi<K>(rec_unpack(rec[io.cell(0, -vy, -vz)]), 1.f, un[vel_rank<M>(K, false)]);
             } else if constexpr (vx > 0) {
                 constexpr int K2 = xvel_partner<M>(K);
                 const Rec r = rec_unpack(rec[io.cell(0, -vy, -vz)]);
@@ -494,20 +487,11 @@ struct RecX {
     }
     // after a barrier: add every velocity's phi to the gathered populations
     template <int K = 0, class IO>
-    __device__ static void collect(const IO &io, const float (*xs)[RB], const float (&un)[kN][kHeld],
+    __device__ static void collect(const IO &io, const float (*xs)[RB], const float (&un)[kN][P],
                                    float (&f)[M::Q]) {
         if constexpr (K < S::kNV) {
             if constexpr (S::vel(K, 0) == 0) {
-                const float(&h)[kHeld] = un[vel_rank<M>(K, false)];
-                if constexpr (kHoldPhi) {
-                    S::template apply<K>(f, h);
-                } else {
-                    const u32x4 w = {__float_as_uint(h[0]), __float_as_uint(h[1]), __float_as_uint(h[2]),
-                                     __float_as_uint(h[3])};
-                    float u[P];
-                    S::template phi<K>(rec_unpack(w), 1.f, u);
-                    S::template apply<K>(f, u);
-                }
+                S::template apply<K>(f, un[vel_rank<M>(K, false)]);
             } else {
                 const uint32_t own = io.slot(0);
                 float u[P];

@@ -133,11 +133,12 @@ __global__ __launch_bounds__(TB) void row_step_kernel(StepArgs a) {
     const uint32_t c = row * a.nx + (live ? x : 0u);
     const size_t N = a.N;
     RowIO<M, ST, RB> io(a.pop, a.pl, a.ny, a.nz, row, x);
-    // shifted storage: the LDS forms exchange the x-shifted records (RecX)
-    constexpr bool XREC = ST::kShift && !DIRECT;
+    // shifted storage: the LDS forms of MM and the difference form exchange
+    // the x-shifted records (RecX)
     using RX = RecX<M, RB>;
+    constexpr bool XREC = ST::kShift && !DIRECT && RX::kUse;
     __shared__ float xs[XREC ? RX::kX * RX::P : 1][XREC ? RB : 1];
-    float un[XREC ? RX::kN : 1][RX::kHeld];
+    float un[XREC ? RX::kN : 1][RX::P];
     if constexpr (XREC) RX::publish(io, static_cast<const u32x4 *>(a.rec[ODD ? 0 : 1]), xs, un);
     float f[M::Q];
     if (DIRECT) {

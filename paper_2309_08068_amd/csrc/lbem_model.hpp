@@ -463,9 +463,10 @@ __device__ __forceinline__ u32x4 rec_pack(const float E[3], const float B[3], fl
 // Per model: the distinct moving velocities k (every shifted population
 // belongs to exactly one), phi<k>(R, s, u): the kNPhi distinct values of
 // s * phi_q(R) over the populations q of k, and apply<k>(f, u): f_q += those
-// values.  The products and sums are written out with explicit FMAs, so that
-// a value computed by one thread and handed to another (see the row form's
-// record exchange) has the same bits as one computed and applied in place.
+// values.  MM's and the difference form's products and sums are written out
+// with explicit FMAs, so that a value computed by one thread and handed to
+// another (the row form's record exchange) has the same bits as one computed
+// and applied in place.
 template <class M>
 struct Shift;
 template <>
@@ -523,15 +524,14 @@ struct Shift<HV> {
     static constexpr int kNV = 6;    // k = i; populations 3i + a, 18 + 3i + a
     static constexpr int kNPhi = 6;  // e_a, h_a
     __host__ __device__ static constexpr int vel(int k, int a) { return kHVV[k][a]; }
+    // (HV's phi never passes between threads, so the compiler may contract it)
     template <int K>
     __device__ static void phi(const Rec &r, float s, float (&u)[kNPhi]) {
-        // e_eq = (3 eps_r E - v x B / mu_r) / 6,  h_eq = (B + 3 v x E) / 6; the
-        // cross products of an axis velocity are single signed terms (exact)
-        const float ke = 0.5f * r.eps, km = (1.f / 6.f) * r.imu;
+        // e_eq = (3 eps_r E - v x B / mu_r) / 6,  h_eq = (B + 3 v x E) / 6
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            u[a] = s * __builtin_fmaf(ke, r.E[a], -(km * hv_vcross<K>(r.B, a)));
-            u[3 + a] = s * __builtin_fmaf(0.5f, hv_vcross<K>(r.E, a), (1.f / 6.f) * r.B[a]);
+            u[a] = s * (0.5f * r.eps * r.E[a] - (1.f / 6.f) * r.imu * hv_vcross<K>(r.B, a));
+            u[3 + a] = s * ((1.f / 6.f) * r.B[a] + 0.5f * hv_vcross<K>(r.E, a));
         }
     }
     template <int K>
