@@ -618,11 +618,16 @@ def test_unstable_and_invalid_media_rejected():
                                                  ("hv", "f32", (256, 20, 13)), ("mm", "bf16_shifted", (256, 20, 13)),
                                                  ("hv", "f16_shifted", (256, 20, 13)), ("mmd", "f32", (256, 20, 13)),
                                                  ("mmd", "bf16_shifted", (256, 20, 13)), ("mm", "f32", (200, 20, 13)),
-                                                 ("hv", "bf16_shifted", (200, 20, 13))])
+                                                 ("hv", "bf16_shifted", (200, 20, 13)),
+                                                 ("mm", "bf16_shifted", (200, 20, 13)),
+                                                 ("mmd", "f16_shifted", (193, 9, 17))])
 def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage, shape):
     """Every (address form, blocks-per-CU cap) choice of the step kernel gives
     the same bits; autotune leaves the state as it found it (two layout
-    chunks; a 200-cell row in a 256-thread block)."""
+    chunks; a 200-cell row in a 256-thread block).  For the shifted formats of
+    MM and the difference form, the LDS forms hand the x-shifted records' phi
+    values between threads and the direct forms evaluate them in place, idle
+    threads and the periodic wrap of the row included."""
     p = random_problem(model, shape, seed=21)
     ref = None
     for form in ((0, 0), (1, 1), (0, 1), (2, 2), (2, 1), (4, 5), (6, 4), (3, 3), (7, 1)):
