@@ -620,7 +620,9 @@ def test_unstable_and_invalid_media_rejected():
                                                  ("mmd", "bf16_shifted", (256, 20, 13)), ("mm", "f32", (200, 20, 13)),
                                                  ("hv", "bf16_shifted", (200, 20, 13)),
                                                  ("mm", "bf16_shifted", (200, 20, 13)),
-                                                 ("mmd", "f16_shifted", (193, 9, 17))])
+                                                 ("mmd", "f16_shifted", (193, 9, 17)),
+                                                 ("mm", "bf16_shifted", (384, 6, 11)),
+                                                 ("mmd", "bf16_shifted", (450, 4, 9))])
 def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage, shape):
     """Every (address form, blocks-per-CU cap) choice of the step kernel gives
     the same bits; autotune leaves the state as it found it (two layout
