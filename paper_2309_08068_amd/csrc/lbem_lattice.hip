@@ -862,9 +862,13 @@ size_t lbem::lds_pad_for(const void *kernel, int cap) {
     if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
         lds_cu <= 0)
         return 0;
+    int lds_block = 0;  // per-workgroup limit (160 KB on gfx950)
+    if (hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        size_t(lds_block) <= attr.sharedSizeBytes)
+        return 0;
     const size_t per_block = size_t(lds_cu) / size_t(cap + 1) + 1;  // cap blocks fit, cap + 1 do not
     const size_t need = per_block > attr.sharedSizeBytes ? per_block - attr.sharedSizeBytes : 0;
-    return std::min<size_t>(need, 65536 - attr.sharedSizeBytes);
+    return std::min<size_t>(need, size_t(lds_block) - attr.sharedSizeBytes);
 }
 
 uint32_t lbem::step_segments(const lbem_lattice *lat, int odd) {
