@@ -317,6 +317,14 @@ lbem_status lbem_load_state(lbem_lattice *lat, const void *src, int64_t t);
 lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, int32_t K, int32_t keep,
                                         size_t *bytes);
 
+/* The largest keep (1 <= keep <= ceil(nsteps / K)) whose adjoint workspace
+ * fits in budget_bytes, written to *keep (host int32): the schedule with the
+ * least recomputation a given amount of device memory allows.  Host-side
+ * only, no GPU work.  LBEM_ENOMEM if even keep = 1 needs more than the
+ * budget; otherwise as lbem_adjoint_workspace_size. */
+lbem_status lbem_adjoint_keep(const lbem_desc *desc, int64_t nsteps, int32_t K, size_t budget_bytes,
+                              int32_t *keep);
+
 /* Run nsteps steps from the current state (time level t0) recording
  * checkpoints in ws, and write L (sum over the collided states of the plane
  * det_z of |E|^2, FP64) to loss (dev double [1]).  Leaves the lattice at

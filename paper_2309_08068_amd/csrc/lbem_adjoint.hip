@@ -530,6 +530,24 @@ lbem_status lbem_adjoint_workspace_size(const lbem_desc *desc, int64_t nsteps, i
     return LBEM_OK;
 }
 
+lbem_status lbem_adjoint_keep(const lbem_desc *desc, int64_t nsteps, int32_t K, size_t budget_bytes,
+                              int32_t *keep) {
+    size_t dummy;
+    lbem_status st = lbem_adjoint_workspace_size(desc, nsteps, K, 1, &dummy);
+    if (st) return st;
+    if (!keep) return fail(LBEM_EINVAL, "keep is NULL");
+    if (dummy > budget_bytes) return fail(LBEM_ENOMEM, "even keep = 1 needs %zu bytes", dummy);
+    // the workspace grows with keep: the largest keep that fits, by bisection
+    int64_t lo = 1, hi = std::min<int64_t>((nsteps + K - 1) / K, INT32_MAX);
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (adj_layout(desc, nsteps, K, int32_t(mid)).total <= budget_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    *keep = int32_t(lo);
+    return LBEM_OK;
+}
+
 lbem_status lbem_adjoint_forward(lbem_lattice *lat, int64_t nsteps, int32_t K, int32_t keep, int32_t det_z, void *ws,
                                  size_t ws_bytes, double *loss) {
     if (!lat || !ws || !loss) return fail(LBEM_EINVAL, "null argument");

@@ -54,6 +54,7 @@ SIGNATURES = {
     "lbem_autotune": (_I32, [_P, _I32, _P]),
     "lbem_load_state": (_I32, [_P, _P, _I64]),
     "lbem_adjoint_workspace_size": (_I32, [_P, _I64, _I32, _I32, C.POINTER(_SZ)]),
+    "lbem_adjoint_keep": (_I32, [_P, _I64, _I32, _SZ, C.POINTER(_I32)]),
     "lbem_adjoint_forward": (_I32, [_P, _I64, _I32, _I32, _I32, _P, _SZ, _P]),
     "lbem_adjoint_backward": (_I32, [_P, _P, _SZ, _P, _P, _D, _P, _P]),
     "lbem_adjoint": (_I32, [_P, _I64, _I32, _I32, _I32, _P, _P, _D, _P, _P, _P, _P, _SZ]),
@@ -339,6 +340,13 @@ class Lattice:
         c = (C.c_int32 * 2)()
         check(self.lib.lbem_get_adjoint_tuning(self.h, f, c))
         return list(f), list(c)
+
+    def adjoint_keep(self, nsteps: int, K: int, budget_bytes: int) -> int:
+        """The largest keep whose adjoint workspace fits in budget_bytes."""
+        keep = C.c_int32()
+        check(self.lib.lbem_adjoint_keep(C.byref(self._desc), int(nsteps), int(K), int(budget_bytes),
+                                         C.byref(keep)))
+        return keep.value
 
     def adjoint_workspace(self, nsteps: int, K: int, keep: int = 1) -> torch.Tensor:
         size = C.c_size_t()

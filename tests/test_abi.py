@@ -188,3 +188,35 @@ def test_adjoint_needs_fp32_storage(lib):
         assert b"FP32" in lib.lbem_last_error()
     d = lbem.desc("hv", (16, 16, 16))
     assert lib.lbem_adjoint_workspace_size(C.byref(d), 10, 2, 1, C.byref(out)) == 0
+
+
+@pytest.mark.parametrize("model,shape,nsteps,K", [("mm", (128, 128, 256), 1500, 50), ("hv", (16, 16, 16), 41, 7),
+                                                  ("mmd", (256, 2, 3), 10, 10)])
+def test_adjoint_keep_is_largest_that_fits(lib, model, shape, nsteps, K):
+    """lbem_adjoint_keep returns the largest keep whose workspace fits the
+    budget: exact fits, one byte short, everything, and too little."""
+    d = lbem.desc(model, shape)
+    S = -(-nsteps // K)
+
+    def size(keep):
+        out = C.c_size_t()
+        assert lib.lbem_adjoint_workspace_size(C.byref(d), nsteps, K, keep, C.byref(out)) == 0
+        return out.value
+
+    def keep_for(budget):
+        k = C.c_int32()
+        st = lib.lbem_adjoint_keep(C.byref(d), nsteps, K, budget, C.byref(k))
+        return st, k.value
+
+    sizes = [size(k) for k in range(1, S + 1)]
+    assert sizes == sorted(sizes) and (S == 1 or sizes[-1] > sizes[0])
+    for k in sorted({1, (S + 1) // 2, S}):
+        assert keep_for(sizes[k - 1]) == (0, k)
+        if k > 1 and sizes[k - 2] < sizes[k - 1]:
+            assert keep_for(sizes[k - 1] - 1) == (0, k - 1)
+    assert keep_for(1 << 62) == (0, S)
+    st, _ = keep_for(sizes[0] - 1)
+    assert lbem.STATUS[st] == "LBEM_ENOMEM"
+    k = C.c_int32()
+    assert lbem.STATUS[lib.lbem_adjoint_keep(C.byref(d), nsteps, K, 1 << 40, None)] == "LBEM_EINVAL"
+    assert lbem.STATUS[lib.lbem_adjoint_keep(C.byref(d), 0, K, 1 << 40, C.byref(k))] == "LBEM_EINVAL"

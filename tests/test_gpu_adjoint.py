@@ -57,6 +57,22 @@ def gpu_grad(shape, d, nsteps, det_z, K, model="mm", keep=1):
 
 
 @pytest.mark.parametrize("model", ["mm", "hv", "mmd"])
+def test_default_keep_holds_every_frame_and_matches_keep_one(model):
+    """DetectorProblem's default keep (0) holds as many segments of frames as
+    half the free device memory allows (every one, on this lattice), so the
+    backward recomputes nothing; the loss and gradients are those of keep = 1,
+    whose backward recomputes all but the last segment."""
+    shape, nsteps, K = (128, 3, 10), 23, 5
+    d = smooth_case(shape, 8)
+    res = [gpu_grad(shape, d, nsteps, shape[2] - 3, K, model, keep) for keep in (0, 1)]
+    assert res[0][0] == res[1][0]
+    for a, b in zip(res[0][1:], res[1][1:]):
+        assert np.array_equal(a, b)
+    lat = lbem.Lattice(model, shape)
+    assert lat.adjoint_keep(nsteps, K, torch.cuda.mem_get_info()[0] // 2) == -(-nsteps // K)
+
+
+@pytest.mark.parametrize("model", ["mm", "hv", "mmd"])
 @pytest.mark.parametrize("shape,nsteps,K,keep", [((6, 5, 16), 40, 7, 1), ((6, 5, 16), 41, 41, 1),
                                                  ((6, 5, 16), 40, 7, 3), ((6, 5, 16), 40, 7, 6),
                                                  ((128, 2, 12), 25, 4, 2), ((256, 1, 6), 17, 5, 1),
