@@ -622,7 +622,9 @@ def test_unstable_and_invalid_media_rejected():
                                                  ("mm", "bf16_shifted", (200, 20, 13)),
                                                  ("mmd", "f16_shifted", (193, 9, 17)),
                                                  ("mm", "bf16_shifted", (384, 6, 11)),
-                                                 ("mmd", "bf16_shifted", (450, 4, 9))])
+                                                 ("mmd", "bf16_shifted", (450, 4, 9)),
+                                                 ("mm", "f16_shifted", (120, 9, 17)),
+                                                 ("mmd", "bf16_shifted", (128, 40, 9))])
 def test_launch_tuning_is_bit_identical_and_autotune_restores_state(model, storage, shape):
     """Every (address form, blocks-per-CU cap) choice of the step kernel gives
     the same bits; autotune leaves the state as it found it (two layout
